@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Benchmark of the SSFM march on one MI355X.
+
+Workload: the 256 x 256 grid, 1000 z-step, 30 mm, 30 W, xi = 2.84 march with
+depleted pump, linear and two-photon absorption and input phase noise
+(complex64).  One benchmark step is one whole march of that crystal (all
+passes of every z-step, the mismatch-phase table and the exit powers), started
+from the seeded input field that is resident in HBM.
+
+Printed JSON line:
+  value        cell-steps/s = nx * ny * nz * steps / wall time of the timed steps
+  roofline     dominant kernel (per-launch HIP events, timing mode): algorithmic
+               bytes per launch (both complex64 fields read and written once,
+               32 B per cell) / average launch duration, against 8 TB/s
+  cpu_baseline the FP64 oracle on a bounded sample of the same workload
+  extras       batched and forward+adjoint throughput when those paths run
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 2]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "SSFM cell-steps/s (Nx·Ny·Nz/s) fwd, fwd+adjoint, batched; % HBM roofline"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2410_04994_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, launch_bytes: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except ValueError:
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    ent = rec.get("kernels", {}).get(kernel)
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, sample_steps: int):
+    """Time the FP64 oracle (as it stands) on the first `sample_steps` z-steps."""
+    import numpy as np
+    import workloads
+    from oracle import beams, ssfm
+    p = dict(wl.params())
+    p["nz"] = wl.nz
+    a0 = beams.input_pump(p, wl.power, wl.w0, wl.focus, workloads.phase_noise(wl))
+    a0 = a0.astype(np.complex64)
+    b0 = np.zeros_like(a0)
+    t = time.perf_counter()
+    ssfm.propagate(p, a0, b0, s_end=sample_steps)
+    dt = time.perf_counter() - t
+    return {"value": wl.nx * wl.ny * sample_steps / dt, "unit": "cell-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{wl.name}: first {sample_steps} of {wl.nz} z-steps, numpy FP64, one thread"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-sample-steps", type=int, default=300)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(independent instances shard across GPUs with no exchange; see the design notes)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    import workloads
+    from paper_2410_04994_amd import Plan, beams
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    wl = workloads.c2_plain_c64()
+    plan = Plan(wl.params(), "c64")
+    theta = torch.from_numpy(workloads.phase_noise(wl)).to(dev)
+    a_in = beams.pump_for(wl, theta=theta, dtype=torch.complex64, device=dev)
+    b_in = torch.zeros_like(a_in)
+    a = torch.empty_like(a_in)
+    b = torch.empty_like(b_in)
+    ws = plan.workspace(device=dev)
+    powers = torch.empty(2, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        a.copy_(a_in)
+        b.copy_(b_in)
+        plan.propagate(a, b, workspace=ws, powers=powers, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ms_per_step = ms / args.steps
+    value = wl.cell_steps * args.steps / (ms / 1e3)
+
+    # per-kernel durations of the same march (timing mode: same kernels, one
+    # event pair around each launch)
+    plan.set_timing(True)
+    for _ in range(args.steps):
+        step()
+    kt = plan.kernel_times()
+    plan.set_timing(False)
+    row_avg = kt["row_ms"] / max(1, kt["row_n"])
+    col_avg = kt["col_ms"] / max(1, kt["col_n"])
+    dom, avg_ms = ("row_pass", row_avg) if kt["row_ms"] >= kt["col_ms"] else ("col_pass", col_avg)
+    launch_bytes = 32.0 * wl.nx * wl.ny
+    achieved = launch_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom, launch_bytes)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": dom, "avg_launch_us": round(avg_ms * 1e3, 3),
+                "algorithmic_bytes_per_launch": int(launch_bytes),
+                "row_pass_avg_us": round(row_avg * 1e3, 3), "col_pass_avg_us": round(col_avg * 1e3, 3),
+                "whole_march_frac_at_64B": round(value * 64.0 / (HBM_PEAK_GBS * 1e9), 4)}
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "cell-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": wl.name, "grid": [wl.nx, wl.ny], "nz": wl.nz,
+                      "crystal_m": wl.lcr, "power_W": wl.power, "xi": wl.xi,
+                      "schedule": plan.describe()},
+           "roofline": roofline}
+    if not args.no_extras:
+        try:
+            from paper_2410_04994_amd import extras
+            out["extras"] = extras.run_all(dev)
+        except Exception as exc:  # extras must never hide the main line
+            out["extras"] = {"error": f"{type(exc).__name__}: {exc}"}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

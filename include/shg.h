@@ -1,0 +1,194 @@
+/* shg.h - C ABI of the MI355X split-step Fourier (SSFM) march of the coupled
+ * second-harmonic-generation equations.
+ *
+ * What is computed.  The fundamental A_F and second-harmonic A_SH envelopes
+ * obey the coupled-wave equations of Sec. 2.1 (Eqs. 1-2) with the accumulated
+ * mismatch phase of Eq. 3; the march is the split-step Fourier method of
+ * Sec. 3 (Eqs. 11-15): each z-step applies the nonlinear operator N over dz/2
+ * by classical RK4, the linear operator L (paraxial diffraction and linear
+ * absorption) over dz in Fourier space (Appendix A, Eqs. A.3-A.5), and N over
+ * dz/2 again (Eq. 14, order N/2 - L - N/2).  Readings of the printed
+ * equations used here:
+ *   - coupling kappa_F = 2 pi d / (n_F lambda_F), kappa_SH = 2 pi d / (n_SH lambda_F)
+ *     (the printed lambda_SH in the SH coefficient breaks Manley-Rowe energy
+ *     conservation with I = eps0 c n |A|^2 / 2 of Sec. 2.2);
+ *   - two-photon absorption acts on intensity, beta~_j = beta_j eps0 c n_j / 2;
+ *   - the linear loss alpha_j is exact inside the Fourier-space propagator;
+ *   - with a temperature field, dk = dk_s + ddk_dT (T - t_ref) per cell and a
+ *     thermal-lens term -i (2 pi / lambda_j) dn_dT (T - t_ref) A_j, with T given
+ *     at each step's mid-plane;
+ *   - SHG_UNDEPLETED zeroes the whole nonlinear part of dA_F/dz (Sec. 5.1).
+ *
+ * Conventions.
+ *   - SI units throughout: m, W, rad/m, 1/m (intensity absorption), m/W, K.
+ *   - Fields are row-major [ny][nx] interleaved complex (re, im), x fastest:
+ *     complex64 (float pairs) for SHG_C64 plans, complex128 for SHG_C128.
+ *     Sample (m, n) sits at x = (m - nx/2) dx, y = (n - ny/2) dy, dx = lx/nx:
+ *     the window is periodic.
+ *   - All array arguments are DEVICE pointers owned by the caller.  The
+ *     library never frees or retains them beyond the call.
+ *   - Calls are asynchronous on the caller's HIP stream (passed as void*,
+ *     NULL = default stream).  A plan must not be used on two streams at once.
+ *   - Every entry point returns a status code; arguments are validated before
+ *     anything is launched, and on error nothing has been enqueued.  A device
+ *     fault of an earlier launch surfaces as SHG_EDEVICE.  shg_last_error()
+ *     gives a message for the calling thread.
+ */
+#ifndef SHG_H
+#define SHG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct shg_plan shg_plan;
+
+typedef enum { SHG_C64 = 0, SHG_C128 = 1 } shg_dtype;
+
+enum {
+  SHG_OK = 0,
+  SHG_EINVAL = 1,       /* invalid argument (message says which)            */
+  SHG_EUNSUPPORTED = 2, /* valid but not built here (e.g. grid size)        */
+  SHG_ENOMEM = 3,       /* device allocation failed                          */
+  SHG_EDEVICE = 4,      /* HIP runtime error, including earlier device faults */
+  SHG_ESTATE = 5        /* NULL or destroyed plan                            */
+};
+
+/* flags */
+enum {
+  SHG_UNDEPLETED = 1u << 0, /* undepleted pump: dA_F/dz has no nonlinear part */
+  SHG_NO_GRAPH = 1u << 1    /* launch passes one by one instead of replaying a
+                               cached HIP graph of the whole march              */
+};
+
+typedef struct {
+  int32_t nx, ny, nz;     /* nx, ny powers of two in [16, 512]; nz >= 1        */
+  double lx, ly;          /* transverse window widths [m]                      */
+  double lcr;             /* crystal length [m]; dz = lcr / nz                 */
+  double lambda_f;        /* fundamental vacuum wavelength [m]; SH at half     */
+  double n_f, n_sh;       /* refractive indices                                */
+  double d_eff;           /* effective nonlinear coefficient [m/V]            */
+  double alpha_f, alpha_sh; /* linear intensity absorption [1/m]               */
+  double beta_f, beta_sh; /* two-photon absorption [m/W]                       */
+  double dk0;             /* phase mismatch [rad/m] when no per-step profile   */
+  double ddk_dT;          /* d(dk)/dT [rad/(m K)], temperature field only      */
+  double dn_dT;           /* thermo-optic coefficient [1/K], both waves        */
+  double t_ref;           /* reference temperature [K]                         */
+  uint32_t flags;         /* SHG_UNDEPLETED | SHG_NO_GRAPH                      */
+  int32_t checkpoint_every; /* adjoint checkpoint interval K (0 -> 32)         */
+} shg_params;
+
+/* Create a plan: validates the parameters, builds the FP64 propagator and
+ * twiddle tables (rounded once to the plan's precision where the kernels use
+ * that precision), chooses launch schedules, and allocates the plan's small
+ * device tables on the current HIP device.
+ * Errors: SHG_EINVAL (NULL pointer, nx/ny not a power of two in [16, 512],
+ * nz < 1, non-positive or non-finite lengths/indices/wavelength, negative
+ * absorption), SHG_ENOMEM, SHG_EDEVICE.  *out is NULL on error. */
+int shg_plan_create(shg_plan **out, const shg_params *p, shg_dtype dtype);
+
+/* Release the plan and its device tables.  NULL is accepted (returns SHG_OK).
+ * The caller must have synchronised the stream of the plan's last call. */
+int shg_plan_destroy(shg_plan *plan);
+
+/* Bytes of device workspace needed by shg_propagate (for_adjoint = 0) or by
+ * shg_propagate_adjoint (for_adjoint = 1).  Returns 0 for a NULL plan. */
+size_t shg_workspace_bytes(const shg_plan *plan, int for_adjoint);
+
+/* March steps [s_begin, s_end) of the crystal in place (Eq. 14 per step).
+ *   a_f, a_sh  in: fields at z = s_begin dz; out: fields at z = s_end dz
+ *   dk_z       [nz] double per-step mismatch, or NULL for params.dk0
+ *   temp       [nz][ny][nx] mid-plane temperature samples in the plan's real
+ *              type (float for C64, double for C128), or NULL for none
+ *   workspace  shg_workspace_bytes(plan, 0) bytes, or NULL to use a buffer
+ *              the plan allocates on first use and keeps
+ *   powers     double[2] {P_F, P_SH} at z = s_end dz (P = int eps0 c n |A|^2/2
+ *              dA, Sec. 2.2), or NULL
+ *   stream     hipStream_t as void*
+ * Errors: SHG_ESTATE, SHG_EINVAL (NULL field, 0 <= s_begin < s_end <= nz
+ * violated), SHG_ENOMEM, SHG_EDEVICE. */
+int shg_propagate(shg_plan *plan, void *a_f, void *a_sh, const double *dk_z,
+                  const void *temp, int32_t s_begin, int32_t s_end,
+                  void *workspace, double *powers, void *stream);
+
+/* Gradient of a real loss L through the whole march (steps [0, nz)).
+ * The loss is L = Re<g_f_out, A_F(L)> + Re<g_sh_out, A_SH(L)>
+ *               + w[0] P_F(L) + w[1] P_SH(L)  (to first order),
+ * with complex gradients in the convention g = dL/dRe + i dL/dIm.
+ *   a_f_in, a_sh_in    fields at z = 0 (not modified)
+ *   dk_z, temp         as for shg_propagate
+ *   g_f_out, g_sh_out  seeds dL/dA(L), or NULL for zero
+ *   power_weights      device double[2] {w_F, w_SH}, or NULL for zero
+ *   g_f_in, g_sh_in    out: dL/dA(0) (same layout as the fields)
+ *   g_dk_z             out: [nz] double dL/d dk_s, or NULL
+ *   g_t_moments        out: double[2] {sum dL/dT (T - t_ref), sum dL/dT}
+ *                      (temp given), or NULL
+ *   a_f_out, a_sh_out  out: forward fields at z = L, or NULL
+ *   powers             out: double[2] forward exit powers, or NULL
+ *   workspace          shg_workspace_bytes(plan, 1) bytes (required)
+ * Fields are checkpointed every params.checkpoint_every steps and recomputed.
+ * Errors: as shg_propagate; SHG_EINVAL also for a NULL workspace. */
+int shg_propagate_adjoint(shg_plan *plan, const void *a_f_in, const void *a_sh_in,
+                          const double *dk_z, const void *temp,
+                          const void *g_f_out, const void *g_sh_out,
+                          const double *power_weights, void *g_f_in, void *g_sh_in,
+                          double *g_dk_z, double *g_t_moments, void *a_f_out,
+                          void *a_sh_out, double *powers, void *workspace,
+                          void *stream);
+
+/* March n independent instances (each over its whole crystal) in one
+ * replayable launch sequence.  Plans may differ in every parameter (grid size,
+ * nz, coupling, mismatch) but must share the dtype and must not use a
+ * temperature field.  Instances advance in lock-step passes grouped by grid
+ * size; an instance stops after its own nz steps.
+ *   plans[i], a_f[i], a_sh[i]  as for shg_propagate (fields updated in place)
+ *   dk_z[i]                    per-instance [nz_i] profile, or NULL entries /
+ *                              NULL array for the plans' dk0
+ *   workspace                  shg_batch_workspace_bytes(...) bytes, or NULL
+ *                              for a library-owned buffer kept by plans[0]
+ *   powers                     [n][2] double exit powers, or NULL
+ * Errors: SHG_EINVAL (n < 1, NULL arrays/entries, mixed dtypes, temperature
+ * flags), SHG_ENOMEM, SHG_EDEVICE. */
+int shg_propagate_batch(int32_t n, shg_plan *const *plans, void *const *a_f,
+                        void *const *a_sh, const double *const *dk_z,
+                        void *workspace, double *powers, void *stream);
+
+/* Workspace bytes for shg_propagate_batch over these plans (0 on error). */
+size_t shg_batch_workspace_bytes(int32_t n, shg_plan *const *plans);
+
+/* Force launch schedules (used by the autotuner and tests).  row_e / col_e:
+ * elements per thread of the row / column transforms (2, 4, 8, 16); row_wg:
+ * threads per row-pass block; col_tc: columns per column-pass block.  Zero
+ * keeps the current choice.  Errors: SHG_EUNSUPPORTED for a schedule that is
+ * not built or does not fit the grid. */
+int shg_plan_set_schedule(shg_plan *plan, int32_t row_e, int32_t row_wg,
+                          int32_t col_e, int32_t col_tc);
+
+/* Per-kernel timing for measurement.  While enabled, shg_propagate launches
+ * every pass individually (no cached graph) with a HIP start/stop event pair
+ * bracketing each kernel.  Enabling or disabling clears the record. */
+int shg_plan_set_timing(shg_plan *plan, int32_t enable);
+
+/* Totals of the timed launches since the last query, then clears them:
+ * out[0] = row-pass milliseconds, out[1] = row-pass launches,
+ * out[2] = column-pass milliseconds, out[3] = column-pass launches.
+ * Synchronises with the recorded events.  Errors: SHG_ESTATE, SHG_EINVAL,
+ * SHG_EDEVICE. */
+int shg_plan_kernel_times(shg_plan *plan, double *out);
+
+/* Write a one-line description of the plan's schedule into buf (NUL
+ * terminated, truncated to len).  Returns SHG_OK or SHG_ESTATE. */
+int shg_plan_describe(const shg_plan *plan, char *buf, size_t len);
+
+/* Message of the last failed call on this thread ("" if none).  Valid until
+ * the next call on this thread. */
+const char *shg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHG_H */

@@ -144,7 +144,7 @@ def step_mismatch(p: dict, s: int, dk_z: Optional[np.ndarray], temp: Optional[np
 
 def power(a: np.ndarray, n: float, dx: float, dy: float) -> float:
     """Beam power P = int I dA with I = eps0 c n |A|^2 / 2 (Sec. 2.2)."""
-    return float(EPS0 * C_LIGHT * n / 2.0 * dx * dy * np.sum(np.abs(a) ** 2))
+    return float(EPS0 * C_LIGHT * n / 2.0 * dx * dy * np.sum(np.abs(np.asarray(a, np.complex128)) ** 2))
 
 
 def propagate(p: dict, a_f: np.ndarray, a_sh: np.ndarray, dk_z: Optional[np.ndarray] = None,

@@ -1,0 +1,261 @@
+"""ctypes binding of the C ABI in include/shg.h.
+
+Argument marshalling only: every step of the march runs in the HIP library.
+Tensors are torch CUDA (HIP) tensors; the binding passes their device pointers
+and the current stream.  There is no CPU fallback: if libshg.so is missing or
+a tensor is not on the GPU the call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libshg.so")
+
+SHG_C64, SHG_C128 = 0, 1
+SHG_OK, SHG_EINVAL, SHG_EUNSUPPORTED, SHG_ENOMEM, SHG_EDEVICE, SHG_ESTATE = range(6)
+SHG_UNDEPLETED = 1 << 0
+SHG_NO_GRAPH = 1 << 1
+ERROR_NAMES = {0: "SHG_OK", 1: "SHG_EINVAL", 2: "SHG_EUNSUPPORTED", 3: "SHG_ENOMEM",
+               4: "SHG_EDEVICE", 5: "SHG_ESTATE"}
+
+
+class ShgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class ShgParams(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lcr", ctypes.c_double),
+                ("lambda_f", ctypes.c_double), ("n_f", ctypes.c_double), ("n_sh", ctypes.c_double),
+                ("d_eff", ctypes.c_double), ("alpha_f", ctypes.c_double),
+                ("alpha_sh", ctypes.c_double), ("beta_f", ctypes.c_double),
+                ("beta_sh", ctypes.c_double), ("dk0", ctypes.c_double), ("ddk_dT", ctypes.c_double),
+                ("dn_dT", ctypes.c_double), ("t_ref", ctypes.c_double), ("flags", ctypes.c_uint32),
+                ("checkpoint_every", ctypes.c_int32)]
+
+
+_VP = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_SIGS = {
+    "shg_plan_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(ShgParams), ctypes.c_int]),
+    "shg_plan_destroy": (ctypes.c_int, [_VP]),
+    "shg_workspace_bytes": (ctypes.c_size_t, [_VP, ctypes.c_int]),
+    "shg_propagate": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP]),
+    "shg_propagate_adjoint": (ctypes.c_int, [_VP] * 16 + [_VP]),
+    "shg_propagate_batch": (ctypes.c_int, [_I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "shg_batch_workspace_bytes": (ctypes.c_size_t, [_I32, _VP]),
+    "shg_plan_set_schedule": (ctypes.c_int, [_VP, _I32, _I32, _I32, _I32]),
+    "shg_plan_describe": (ctypes.c_int, [_VP, ctypes.c_char_p, ctypes.c_size_t]),
+    "shg_plan_set_timing": (ctypes.c_int, [_VP, _I32]),
+    "shg_plan_kernel_times": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double)]),
+    "shg_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libshg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is missing: run `python -m paper_2410_04994_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != SHG_OK:
+        raise ShgError(code, load_library().shg_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t, what: str, dtype=None):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{what} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{what} must have dtype {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+PARAM_KEYS = ("nx", "ny", "nz", "lx", "ly", "lcr", "lambda_f", "n_f", "n_sh", "d_eff", "alpha_f",
+              "alpha_sh", "beta_f", "beta_sh", "dk0", "ddk_dT", "dn_dT", "t_ref")
+
+
+def make_params(params: dict, flags: int = 0, checkpoint_every: int = 0) -> ShgParams:
+    p = ShgParams()
+    for k in PARAM_KEYS:
+        setattr(p, k, params.get(k, 0.0) if k not in ("nx", "ny", "nz") else int(params[k]))
+    f = flags
+    if params.get("undepleted"):
+        f |= SHG_UNDEPLETED
+    p.flags = f
+    p.checkpoint_every = int(checkpoint_every)
+    return p
+
+
+class Plan:
+    """Owns an shg_plan.  `params` uses the keys of workloads.Workload.params()."""
+
+    def __init__(self, params: dict, dtype: str = "c64", flags: int = 0, checkpoint_every: int = 0):
+        lib = load_library()
+        self.params = dict(params)
+        self.dtype = dtype
+        self._cp = make_params(params, flags, checkpoint_every)
+        h = _VP()
+        _check(lib.shg_plan_create(ctypes.byref(h), ctypes.byref(self._cp),
+                                   SHG_C64 if dtype == "c64" else SHG_C128))
+        self.handle = h
+        self._ws = {}
+
+    # ------------------------------------------------------------------ helpers
+    @property
+    def complex_dtype(self):
+        torch = _torch()
+        return torch.complex64 if self.dtype == "c64" else torch.complex128
+
+    @property
+    def real_dtype(self):
+        torch = _torch()
+        return torch.float32 if self.dtype == "c64" else torch.float64
+
+    def workspace_bytes(self, adjoint: bool = False) -> int:
+        return int(load_library().shg_workspace_bytes(self.handle, 1 if adjoint else 0))
+
+    def workspace(self, adjoint: bool = False, device=None):
+        """A cached uint8 device buffer of workspace_bytes(adjoint) bytes."""
+        torch = _torch()
+        n = self.workspace_bytes(adjoint)
+        buf = self._ws.get(adjoint)
+        if buf is None or buf.numel() < n:
+            buf = torch.empty(max(n, 1), dtype=torch.uint8, device=device or "cuda")
+            self._ws[adjoint] = buf
+        return buf
+
+    def set_schedule(self, row_e=0, row_wg=0, col_e=0, col_tc=0):
+        _check(load_library().shg_plan_set_schedule(self.handle, row_e, row_wg, col_e, col_tc))
+
+    def set_timing(self, enable: bool):
+        _check(load_library().shg_plan_set_timing(self.handle, 1 if enable else 0))
+
+    def kernel_times(self) -> dict:
+        """Per-kernel event timings since the last query (timing mode only)."""
+        out = (ctypes.c_double * 4)()
+        _check(load_library().shg_plan_kernel_times(self.handle, out))
+        return {"row_ms": out[0], "row_n": int(out[1]), "col_ms": out[2], "col_n": int(out[3])}
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(256)
+        _check(load_library().shg_plan_describe(self.handle, buf, 256))
+        return buf.value.decode()
+
+    def _field(self, t, what):
+        return _ptr(t, what, self.complex_dtype)
+
+    # ------------------------------------------------------------------ calls
+    def propagate(self, a_f, a_sh, dk_z=None, temp=None, s_begin: int = 0, s_end: Optional[int] = None,
+                  workspace=None, powers=None, stream=None):
+        """March [s_begin, s_end) in place; returns the device double[2] powers."""
+        torch = _torch()
+        if s_end is None:
+            s_end = self.params["nz"]
+        if powers is None:
+            powers = torch.empty(2, dtype=torch.float64, device=a_f.device)
+        _check(load_library().shg_propagate(
+            self.handle, self._field(a_f, "a_f"), self._field(a_sh, "a_sh"),
+            _ptr(dk_z, "dk_z", torch.float64), _ptr(temp, "temp", self.real_dtype),
+            int(s_begin), int(s_end), _ptr(workspace, "workspace"),
+            _ptr(powers, "powers", torch.float64), _stream(stream)))
+        return powers
+
+    def adjoint(self, a_f_in, a_sh_in, g_f_out=None, g_sh_out=None, power_weights=None, dk_z=None,
+                temp=None, want_dk=False, want_t=False, workspace=None, stream=None):
+        """Forward + reverse march.  Returns a dict with g_f, g_sh (gradients at
+        z = 0), a_f, a_sh (exit fields), powers, and g_dk / g_t_moments if asked."""
+        torch = _torch()
+        dev = a_f_in.device
+        g_f = torch.empty_like(a_f_in)
+        g_sh = torch.empty_like(a_sh_in)
+        a_f = torch.empty_like(a_f_in)
+        a_sh = torch.empty_like(a_sh_in)
+        powers = torch.empty(2, dtype=torch.float64, device=dev)
+        g_dk = torch.empty(self.params["nz"], dtype=torch.float64, device=dev) if want_dk else None
+        g_t = torch.empty(2, dtype=torch.float64, device=dev) if want_t else None
+        if workspace is None:
+            workspace = self.workspace(adjoint=True, device=dev)
+        _check(load_library().shg_propagate_adjoint(
+            self.handle, self._field(a_f_in, "a_f_in"), self._field(a_sh_in, "a_sh_in"),
+            _ptr(dk_z, "dk_z", torch.float64), _ptr(temp, "temp", self.real_dtype),
+            self._field(g_f_out, "g_f_out"), self._field(g_sh_out, "g_sh_out"),
+            _ptr(power_weights, "power_weights", torch.float64),
+            self._field(g_f, "g_f_in"), self._field(g_sh, "g_sh_in"),
+            _ptr(g_dk, "g_dk_z", torch.float64), _ptr(g_t, "g_t_moments", torch.float64),
+            self._field(a_f, "a_f_out"), self._field(a_sh, "a_sh_out"),
+            _ptr(powers, "powers", torch.float64), _ptr(workspace, "workspace"), _stream(stream)))
+        out = {"g_f": g_f, "g_sh": g_sh, "a_f": a_f, "a_sh": a_sh, "powers": powers}
+        if want_dk:
+            out["g_dk"] = g_dk
+        if want_t:
+            out["g_t_moments"] = g_t
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().shg_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_workspace_bytes(plans: Sequence[Plan]) -> int:
+    arr = (_VP * len(plans))(*[p.handle for p in plans])
+    return int(load_library().shg_batch_workspace_bytes(len(plans), arr))
+
+
+def propagate_batch(plans: Sequence[Plan], a_f: Sequence, a_sh: Sequence, dk_z: Optional[Sequence] = None,
+                    workspace=None, powers=None, stream=None):
+    """March every instance over its whole crystal; returns [n, 2] powers."""
+    torch = _torch()
+    n = len(plans)
+    if powers is None:
+        powers = torch.empty((n, 2), dtype=torch.float64, device=a_f[0].device)
+    hp = (_VP * n)(*[p.handle for p in plans])
+    fa = (_VP * n)(*[p._field(t, "a_f[i]") for p, t in zip(plans, a_f)])
+    fs = (_VP * n)(*[p._field(t, "a_sh[i]") for p, t in zip(plans, a_sh)])
+    dk = None
+    if dk_z is not None:
+        dk = (_VP * n)(*[_ptr(d, "dk_z[i]", torch.float64) for d in dk_z])
+    _check(load_library().shg_propagate_batch(n, hp, fa, fs, dk, _ptr(workspace, "workspace"),
+                                              _ptr(powers, "powers", torch.float64), _stream(stream)))
+    return powers

@@ -1,0 +1,291 @@
+// Forward SSFM kernels for gfx950: the row pass, the column pass, the
+// per-call mismatch-phase table and the exit power reduction.
+//
+// One z-step of Eq. 14 (N/2 - L - N/2) is executed as two passes over both
+// fields, each reading and writing the state once:
+//   row pass    IFFT_x -> N(dz/2) second half of step s-1 -> N(dz/2) first
+//               half of step s -> FFT_x        (one block owns whole rows)
+//   column pass FFT_y -> multiply by the propagator of Eq. A.4 -> IFFT_y
+//                                               (one block owns whole columns)
+// so between passes the state is held in the (q_x, y) mixed domain.  The first
+// row pass of a march skips the IFFT and the second half-step, and the last one
+// skips the first half-step and the FFT.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fft.hpp"
+
+namespace shg {
+
+// ---------------------------------------------------------------- nonlinear step
+// Right-hand side of the nonlinear operator N (Eq. 11 with the coupling and TPA
+// readings documented in shg.h):
+//   fa = cf * b * conj(a) - tf |a|^2 a,   cf = i kappa_F exp(-i phi)
+//   fb = cs * a^2         - ts |b|^2 b,   cs = i kappa_SH exp(+i phi)
+// tf = beta~_F / 2, ts = beta~_SH / 2.
+template <typename R>
+__device__ __forceinline__ void nl_rhs(cx<R> a, cx<R> b, cx<R> cf, cx<R> cs, R tf, R ts,
+                                       bool undepleted, cx<R>& fa, cx<R>& fb) {
+  const cx<R> a2 = {a.re * a.re - a.im * a.im, (a.re + a.re) * a.im};
+  fb = cs * a2 - scale(b, ts * norm2(b));
+  if (undepleted) {
+    fa = {(R)0, (R)0};
+  } else {
+    fa = cf * mul_conj(b, a) - scale(a, tf * norm2(a));
+  }
+}
+
+// Coupling factors at the three distinct stage points of one RK4 half-step.
+template <typename R>
+struct HalfStep {
+  cx<R> cf[3], cs[3];
+};
+
+// e = exp(-i phi): cf = i kappa_F e, cs = i kappa_SH conj(e)
+template <typename R>
+__device__ __forceinline__ HalfStep<R> half_step_coefs(const cx<R>* __restrict__ e, R kf, R ks) {
+  HalfStep<R> h;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const cx<R> ek = e[k];
+    h.cf[k] = {-kf * ek.im, kf * ek.re};
+    h.cs[k] = {ks * ek.im, ks * ek.re};
+  }
+  return h;
+}
+
+// Classical RK4 over one half-step of length h with stage points t0, t0 + h/2,
+// t0 + h/2, t0 + h (Sec. 3; the RK4 of the paper's nonlinear step).
+template <typename R>
+__device__ __forceinline__ void rk4_cell(cx<R>& a, cx<R>& b, const HalfStep<R>& c, R tf, R ts,
+                                         R h, bool und) {
+  const R h2 = h * (R)0.5;
+  cx<R> k1a, k1b, k2a, k2b, k3a, k3b, k4a, k4b;
+  nl_rhs(a, b, c.cf[0], c.cs[0], tf, ts, und, k1a, k1b);
+  nl_rhs(a + scale(k1a, h2), b + scale(k1b, h2), c.cf[1], c.cs[1], tf, ts, und, k2a, k2b);
+  nl_rhs(a + scale(k2a, h2), b + scale(k2b, h2), c.cf[1], c.cs[1], tf, ts, und, k3a, k3b);
+  nl_rhs(a + scale(k3a, h), b + scale(k3b, h), c.cf[2], c.cs[2], tf, ts, und, k4a, k4b);
+  const R h6 = h / (R)6;
+  a = a + scale(k1a + scale(k2a + k3a, (R)2) + k4a, h6);
+  b = b + scale(k1b + scale(k2b + k3b, (R)2) + k4b, h6);
+}
+
+// ---------------------------------------------------------------- row pass
+template <typename R>
+struct RowArgs {
+  cx<R>* a;               // fundamental [ny][nx]
+  cx<R>* b;               // second harmonic [ny][nx]
+  const Tw<R>* tw;        // W_nx^k, k = 0..nx-1
+  const cx<R>* phase;     // [nz][5] exp(-i phi) at z_s + {0, 1/4, 1/2, 3/4, 1} dz
+  double* partials;       // [gridDim.x][2] sums of |A|^2 (last pass), or null
+  int ny;
+  int s_second;           // step whose second half-step runs here, or -1
+  int s_first;            // step whose first half-step runs here, or -1
+  int inv_in;             // apply IFFT_x after loading
+  int fwd_out;            // apply FFT_x before storing
+  R kf, ks;               // kappa_F, kappa_SH
+  R tf, ts;               // beta~_F / 2, beta~_SH / 2
+  R h;                    // dz / 2
+  int undepleted;
+};
+
+template <int G, int WG>
+struct RowShape {
+  static constexpr int rows = WG > G ? WG / G : 1;
+  static constexpr int threads = G * rows;
+};
+
+// Fixed-order block reduction of two doubles; result valid in thread 0.
+template <int T>
+__device__ __forceinline__ void block_sum2(double& x, double& y, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    x += __shfl_down(x, off, 64);
+    y += __shfl_down(y, off, 64);
+  }
+  constexpr int W = (T + 63) / 64;
+  if constexpr (W > 1) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+      red[2 * w] = x;
+      red[2 * w + 1] = y;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      x = 0.0;
+      y = 0.0;
+      for (int i = 0; i < W; ++i) {
+        x += red[2 * i];
+        y += red[2 * i + 1];
+      }
+    }
+  }
+}
+
+template <typename R, int N, int G, int ROWS>
+__global__ void __launch_bounds__(G * ROWS) row_pass(RowArgs<R> p) {
+  constexpr int E = N / G;
+  constexpr int P = padded_len<N>();
+  __shared__ cx<R> lds[ROWS][2][2][P];
+  __shared__ double red[2 * ((G * ROWS + 63) / 64)];
+  const int t = threadIdx.x % G;
+  const int rr = threadIdx.x / G;
+  const int y = blockIdx.x * ROWS + rr;
+  cx<R>* __restrict__ ra = p.a + (size_t)y * N;
+  cx<R>* __restrict__ rb = p.b + (size_t)y * N;
+  cx<R> va[E], vb[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    va[m] = ra[t + G * m];
+    vb[m] = rb[t + G * m];
+  }
+  const LdsView<R, 1> a0{&lds[rr][0][0][0]}, a1{&lds[rr][0][1][0]};
+  const LdsView<R, 1> b0{&lds[rr][1][0][0]}, b1{&lds[rr][1][1][0]};
+  if (p.inv_in) {
+    fft_regs<R, N, G, true, 1>(va, a0, a1, t, p.tw);
+    fft_regs<R, N, G, true, 1>(vb, b0, b1, t, p.tw);
+  }
+  const bool und = p.undepleted != 0;
+  if (p.s_second >= 0) {
+    const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);
+#pragma unroll
+    for (int m = 0; m < E; ++m) rk4_cell(va[m], vb[m], c, p.tf, p.ts, p.h, und);
+  }
+  if (p.s_first >= 0) {
+    const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks);
+#pragma unroll
+    for (int m = 0; m < E; ++m) rk4_cell(va[m], vb[m], c, p.tf, p.ts, p.h, und);
+  }
+  if (p.fwd_out) {
+    fft_regs<R, N, G, false, 1>(va, a0, a1, t, p.tw);
+    fft_regs<R, N, G, false, 1>(vb, b0, b1, t, p.tw);
+  }
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    ra[t + G * m] = va[m];
+    rb[t + G * m] = vb[m];
+  }
+  if (p.partials) {
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      sa += (double)va[m].re * (double)va[m].re + (double)va[m].im * (double)va[m].im;
+      sb += (double)vb[m].re * (double)vb[m].re + (double)vb[m].im * (double)vb[m].im;
+    }
+    block_sum2<G * ROWS>(sa, sb, red);
+    if (threadIdx.x == 0) {
+      p.partials[2 * blockIdx.x] = sa;
+      p.partials[2 * blockIdx.x + 1] = sb;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- column pass
+template <typename R>
+struct ColArgs {
+  cx<R>* f[2];            // fields (0 = F, 1 = SH)
+  const Tw<R>* tw;        // W_ny^k
+  const double* mx[2];    // per wave: exp(2 i pi^2 qx^2 dz / k), interleaved (re, im) [nx]
+  const double* my[2];    // per wave: exp(2 i pi^2 qy^2 dz / k) exp(-alpha dz/2) / (nx ny) [ny]
+  int nx;                 // row pitch in elements
+  int tiles;              // column tiles per field (nx / TC)
+};
+
+// Block b -> (field, tile).  Blocks are dealt to the 8 XCDs round-robin
+// (b mod 8); consecutive tiles share L2 lines when TC < 16, so consecutive
+// tiles are given to blocks on the same XCD.
+__device__ __forceinline__ int xcd_linear_block(int b, int nblk) {
+  return (nblk % 8 == 0) ? (b % 8) * (nblk / 8) + b / 8 : b;
+}
+
+template <typename R, int N, int G, int TC>
+__global__ void __launch_bounds__(G * TC) col_pass(ColArgs<R> p) {
+  constexpr int E = N / G;
+  constexpr int P = padded_len<N>();
+  __shared__ cx<R> lds[2][P * TC];
+  const int c = threadIdx.x % TC;
+  const int t = threadIdx.x / TC;
+  const int lin = xcd_linear_block(blockIdx.x, gridDim.x);
+  const int field = lin / p.tiles;
+  const int tile = lin - field * p.tiles;
+  const int x = tile * TC + c;
+  cx<R>* __restrict__ col = p.f[field] + x;
+  cx<R> v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = col[(size_t)(t + G * m) * p.nx];
+  const LdsView<R, TC> b0{&lds[0][c]}, b1{&lds[1][c]};
+  fft_regs<R, N, G, false, TC>(v, b0, b1, t, p.tw);
+  // diffraction + linear loss (Eq. A.4), product formed in FP64
+  const double* __restrict__ mxp = p.mx[field];
+  const double* __restrict__ myp = p.my[field];
+  const double mxr = mxp[2 * x], mxi = mxp[2 * x + 1];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int qy = t + G * m;
+    const double myr = myp[2 * qy], myi = myp[2 * qy + 1];
+    const double mr = mxr * myr - mxi * myi;
+    const double mi = mxr * myi + mxi * myr;
+    const double vr = (double)v[m].re, vi = (double)v[m].im;
+    v[m] = {(R)(vr * mr - vi * mi), (R)(vr * mi + vi * mr)};
+  }
+  fft_regs<R, N, G, true, TC>(v, b0, b1, t, p.tw);
+#pragma unroll
+  for (int m = 0; m < E; ++m) col[(size_t)(t + G * m) * p.nx] = v[m];
+}
+
+// ---------------------------------------------------------------- phase table
+// Accumulated mismatch phase (Eq. 3) for a mismatch constant within each step:
+// Phi_s = sum_{s' < s} dk_s' dz (FP64 chunked scan in one block), and
+// out[5 s + k] = exp(-i (Phi_s + dk_s k dz / 4)), k = 0..4.
+template <typename R>
+__global__ void __launch_bounds__(256) phase_table(const double* __restrict__ dk_z, double dk0,
+                                                   int nz, double dz, cx<R>* __restrict__ out) {
+  __shared__ double part[256];
+  const int tid = threadIdx.x;
+  const int chunk = (nz + 255) / 256;
+  const int s0 = min(nz, tid * chunk), s1 = min(nz, s0 + chunk);
+  double sum = 0.0;
+  for (int s = s0; s < s1; ++s) sum += (dk_z ? dk_z[s] : dk0) * dz;
+  part[tid] = sum;
+  __syncthreads();
+  if (tid == 0) {
+    double acc = 0.0;
+    for (int i = 0; i < 256; ++i) {
+      const double v = part[i];
+      part[i] = acc;
+      acc += v;
+    }
+  }
+  __syncthreads();
+  double phi = part[tid];
+  for (int s = s0; s < s1; ++s) {
+    const double dk = dk_z ? dk_z[s] : dk0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      double sn, cs;
+      sincos(phi + dk * (0.25 * k * dz), &sn, &cs);
+      out[5 * s + k] = {(R)cs, (R)(-sn)};
+    }
+    phi += dk * dz;
+  }
+}
+
+// ---------------------------------------------------------------- powers
+// Fixed-order sum of the per-block partials; P_j = scale_j * sum |A_j|^2.
+__global__ void __launch_bounds__(256) power_finalize(const double* __restrict__ partials, int n,
+                                                      double scale_f, double scale_sh,
+                                                      double* __restrict__ powers) {
+  __shared__ double red[8];
+  double x = 0.0, y = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    x += partials[2 * i];
+    y += partials[2 * i + 1];
+  }
+  block_sum2<256>(x, y, red);
+  if (threadIdx.x == 0) {
+    powers[0] = x * scale_f;
+    powers[1] = y * scale_sh;
+  }
+}
+
+}  // namespace shg

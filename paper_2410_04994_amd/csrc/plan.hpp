@@ -1,0 +1,85 @@
+// Internal plan object behind the opaque shg_plan handle.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "shg.h"
+
+namespace shg {
+
+struct GraphKey {
+  const void* a;
+  const void* b;
+  const void* dk;
+  const void* ws;
+  const void* powers;
+  int s0, s1;
+  int re, rw, ce, ct;
+  bool operator==(const GraphKey& o) const {
+    return a == o.a && b == o.b && dk == o.dk && ws == o.ws && powers == o.powers && s0 == o.s0 &&
+           s1 == o.s1 && re == o.re && rw == o.rw && ce == o.ce && ct == o.ct;
+  }
+};
+
+struct Plan {
+  static constexpr uint64_t kMagic = 0x5348475f504c414eull;  // "SHG_PLAN"
+  uint64_t magic = 0;
+  shg_params p{};
+  shg_dtype dtype = SHG_C64;
+  int device = 0;
+  int real_bytes = 4;
+  // derived constants (FP64)
+  double dx = 0, dy = 0, dz = 0;
+  double k_f = 0, k_sh = 0, kappa_f = 0, kappa_sh = 0;
+  double tpa_f = 0, tpa_sh = 0, lens_f = 0, lens_sh = 0;
+  double pscale_f = 0, pscale_sh = 0;
+  int ckpt = 32;
+  // device tables
+  void* tw_x = nullptr;          // W_nx^k in the plan's precision
+  void* tw_y = nullptr;          // W_ny^k
+  double* mx[2] = {nullptr, nullptr};
+  double* my[2] = {nullptr, nullptr};
+  // schedule
+  int row_e = 0, row_wg = 0, row_rows = 1;
+  int col_e = 0, col_tc = 1;
+  // library-owned workspaces
+  void* own_ws = nullptr;
+  size_t own_ws_bytes = 0;
+  void* batch_ws = nullptr;
+  size_t batch_ws_bytes = 0;
+  // cached forward graph
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  GraphKey gkey{};
+  // optional per-kernel timing (kind 0 = row pass, 1 = column pass)
+  int timing = 0;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_kind;
+  size_t ev_used = 0;
+  // adjoint state (owned by adjoint.hip)
+  void* adj = nullptr;
+};
+
+// shg.hip
+int fail(int code, const char* fmt, ...);
+int ok();
+int hip_fail(hipError_t e, const char* what);
+int check_plan(const shg_plan* plan);
+int sticky_device_error();
+size_t forward_ws_bytes(const Plan& pl);
+int enqueue_forward(Plan& pl, void* a, void* b, const double* dk_z, int s0, int s1, void* ws,
+                    double* powers, hipStream_t st);
+int ensure_own_ws(Plan& pl, size_t bytes);
+bool row_supported(const Plan& pl, int e, int wg, int* rows);
+bool col_supported(const Plan& pl, int e, int tc);
+
+// adjoint.hip / thermal.hip / batch.hip
+size_t adjoint_ws_bytes(const Plan& pl);
+void free_adjoint(Plan& pl);
+int propagate_temp(Plan& pl, void* a_f, void* a_sh, const double* dk_z, const void* temp, int s0,
+                   int s1, void* ws, double* powers, hipStream_t st);
+
+}  // namespace shg

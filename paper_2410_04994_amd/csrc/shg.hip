@@ -1,0 +1,668 @@
+// C ABI of the SSFM march (include/shg.h): plans, validation, schedules, the
+// forward launch sequence and its cached HIP graph.
+#include "shg.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include <hip/hip_ext.h>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace shg {
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int ok() {
+  g_last_error.clear();
+  return SHG_OK;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? SHG_ENOMEM : SHG_EDEVICE, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- timing
+// Optional per-kernel timing: launches go through hipExtLaunchKernelGGL with a
+// start/stop event pair that brackets the dispatch itself.
+struct LaunchTimer {
+  Plan* pl;
+  // returns false if no event pair could be obtained (then launch untimed)
+  bool next(int kind, hipEvent_t* a, hipEvent_t* b) {
+    if (!pl || !pl->timing) return false;
+    const size_t need = 2 * (pl->ev_used + 1);
+    while (pl->ev_pool.size() < need) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return false;
+      pl->ev_pool.push_back(e);
+    }
+    *a = pl->ev_pool[2 * pl->ev_used];
+    *b = pl->ev_pool[2 * pl->ev_used + 1];
+    if (pl->ev_kind.size() <= pl->ev_used) pl->ev_kind.resize(pl->ev_used + 1);
+    pl->ev_kind[pl->ev_used] = kind;
+    pl->ev_used++;
+    return true;
+  }
+};
+
+template <typename K, typename A>
+static void launch(K kernel, dim3 grid, dim3 block, hipStream_t st, LaunchTimer* tm, int kind,
+                   const A& args) {
+  hipEvent_t e0, e1;
+  if (tm && tm->next(kind, &e0, &e1)) {
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e0, e1, 0, args);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, 0, st, args);
+  }
+}
+
+// ---------------------------------------------------------------- schedules
+template <typename R, int N, int E, int WG>
+constexpr bool row_valid() {
+  if constexpr (E > N) return false;
+  constexpr int G = N / E;
+  constexpr int rows = RowShape<G, WG>::rows;
+  constexpr size_t lds = (size_t)rows * 4 * padded_len<N>() * sizeof(cx<R>);
+  if (G * rows > 1024 || lds > 64 * 1024) return false;
+  if constexpr (sizeof(R) == 8) return (E == 4 || E == 8) && WG == 64;
+  return true;
+}
+
+template <typename R, int N, int E, int TC>
+constexpr bool col_valid() {
+  if constexpr (E > N) return false;
+  constexpr int G = N / E;
+  constexpr size_t lds = (size_t)2 * padded_len<N>() * TC * sizeof(cx<R>);
+  if (G * TC < 32 || G * TC > 512 || lds > 64 * 1024) return false;
+  if constexpr (sizeof(R) == 8) return (E == 4 || E == 8) && G * TC <= 128;
+  return true;
+}
+
+template <typename R, int N, int E, int WG>
+bool row_try(int e, int wg, const RowArgs<R>* a, hipStream_t st, int* rows_out, LaunchTimer* tm) {
+  if constexpr (row_valid<R, N, E, WG>()) {
+    if (e != E || wg != WG) return false;
+    constexpr int G = N / E;
+    using S = RowShape<G, WG>;
+    if (rows_out) *rows_out = S::rows;
+    if (a) {
+      launch(row_pass<R, N, G, S::rows>, dim3(a->ny / S::rows), dim3(S::threads), st, tm, 0, *a);
+    }
+    return true;
+  } else {
+    (void)e; (void)wg; (void)a; (void)st; (void)rows_out; (void)tm;
+    return false;
+  }
+}
+
+template <typename R, int N, int E, int TC>
+bool col_try(int e, int tc, const ColArgs<R>* a, hipStream_t st, LaunchTimer* tm) {
+  if constexpr (col_valid<R, N, E, TC>()) {
+    if (e != E || tc != TC) return false;
+    if (a) {
+      launch(col_pass<R, N, N / E, TC>, dim3(2 * a->tiles), dim3((N / E) * TC), st, tm, 1, *a);
+    }
+    return true;
+  } else {
+    (void)e; (void)tc; (void)a; (void)st; (void)tm;
+    return false;
+  }
+}
+
+template <typename R, int N>
+bool row_dispatch_n(int e, int wg, const RowArgs<R>* a, hipStream_t st, int* rows,
+                    LaunchTimer* tm) {
+  return row_try<R, N, 4, 64>(e, wg, a, st, rows, tm) ||
+         row_try<R, N, 4, 256>(e, wg, a, st, rows, tm) ||
+         row_try<R, N, 8, 64>(e, wg, a, st, rows, tm) ||
+         row_try<R, N, 8, 256>(e, wg, a, st, rows, tm) ||
+         row_try<R, N, 16, 64>(e, wg, a, st, rows, tm) ||
+         row_try<R, N, 16, 256>(e, wg, a, st, rows, tm);
+}
+
+template <typename R, int N>
+bool col_dispatch_n(int e, int tc, const ColArgs<R>* a, hipStream_t st, LaunchTimer* tm) {
+  return col_try<R, N, 4, 1>(e, tc, a, st, tm) || col_try<R, N, 4, 2>(e, tc, a, st, tm) ||
+         col_try<R, N, 4, 4>(e, tc, a, st, tm) || col_try<R, N, 4, 8>(e, tc, a, st, tm) ||
+         col_try<R, N, 4, 16>(e, tc, a, st, tm) || col_try<R, N, 8, 1>(e, tc, a, st, tm) ||
+         col_try<R, N, 8, 2>(e, tc, a, st, tm) || col_try<R, N, 8, 4>(e, tc, a, st, tm) ||
+         col_try<R, N, 8, 8>(e, tc, a, st, tm) || col_try<R, N, 8, 16>(e, tc, a, st, tm) ||
+         col_try<R, N, 16, 1>(e, tc, a, st, tm) || col_try<R, N, 16, 2>(e, tc, a, st, tm) ||
+         col_try<R, N, 16, 4>(e, tc, a, st, tm) || col_try<R, N, 16, 8>(e, tc, a, st, tm) ||
+         col_try<R, N, 16, 16>(e, tc, a, st, tm);
+}
+
+template <typename R>
+bool row_dispatch(int n, int e, int wg, const RowArgs<R>* a, hipStream_t st, int* rows,
+                  LaunchTimer* tm = nullptr) {
+  switch (n) {
+    case 16: return row_dispatch_n<R, 16>(e, wg, a, st, rows, tm);
+    case 32: return row_dispatch_n<R, 32>(e, wg, a, st, rows, tm);
+    case 64: return row_dispatch_n<R, 64>(e, wg, a, st, rows, tm);
+    case 128: return row_dispatch_n<R, 128>(e, wg, a, st, rows, tm);
+    case 256: return row_dispatch_n<R, 256>(e, wg, a, st, rows, tm);
+    case 512: return row_dispatch_n<R, 512>(e, wg, a, st, rows, tm);
+    default: return false;
+  }
+}
+
+template <typename R>
+bool col_dispatch(int n, int e, int tc, const ColArgs<R>* a, hipStream_t st,
+                  LaunchTimer* tm = nullptr) {
+  switch (n) {
+    case 16: return col_dispatch_n<R, 16>(e, tc, a, st, tm);
+    case 32: return col_dispatch_n<R, 32>(e, tc, a, st, tm);
+    case 64: return col_dispatch_n<R, 64>(e, tc, a, st, tm);
+    case 128: return col_dispatch_n<R, 128>(e, tc, a, st, tm);
+    case 256: return col_dispatch_n<R, 256>(e, tc, a, st, tm);
+    case 512: return col_dispatch_n<R, 512>(e, tc, a, st, tm);
+    default: return false;
+  }
+}
+
+// Is (e, wg) a built row schedule for this grid?  rows_out gets rows per block.
+bool row_supported(const Plan& pl, int e, int wg, int* rows) {
+  int r = 0;
+  bool okk = pl.dtype == SHG_C64 ? row_dispatch<float>(pl.p.nx, e, wg, nullptr, nullptr, &r)
+                                 : row_dispatch<double>(pl.p.nx, e, wg, nullptr, nullptr, &r);
+  if (!okk || pl.p.ny % r != 0) return false;
+  if (rows) *rows = r;
+  return true;
+}
+
+bool col_supported(const Plan& pl, int e, int tc) {
+  bool okk = pl.dtype == SHG_C64 ? col_dispatch<float>(pl.p.ny, e, tc, nullptr, nullptr)
+                                 : col_dispatch<double>(pl.p.ny, e, tc, nullptr, nullptr);
+  return okk && pl.p.nx % tc == 0;
+}
+
+// Default schedules: spread a single instance over many blocks (it is latency
+// bound), keep 64-thread blocks.  The autotuner may override.
+void default_schedule(Plan& pl) {
+  const int nx = pl.p.nx, ny = pl.p.ny;
+  const int row_e[] = {8, 4, 16};
+  for (int e : row_e) {
+    if (row_supported(pl, e, 64, &pl.row_rows)) {
+      pl.row_e = e;
+      pl.row_wg = 64;
+      break;
+    }
+  }
+  const int col_e[] = {8, 4, 16};
+  pl.col_e = 0;
+  for (int e : col_e) {
+    if (e > ny) continue;
+    const int g = ny / e;
+    int tc = 64 / g;
+    if (tc < 1) tc = 1;
+    if (tc > 16) tc = 16;
+    while (tc > 1 && nx % tc) tc >>= 1;
+    if (col_supported(pl, e, tc)) {
+      pl.col_e = e;
+      pl.col_tc = tc;
+      break;
+    }
+    if (col_supported(pl, e, 2 * tc)) {
+      pl.col_e = e;
+      pl.col_tc = 2 * tc;
+      break;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- tables
+// W_n^k = exp(-2 pi i k / n) as R hi + lo (evaluated in long double); the lo
+// part is only used in single precision.
+template <typename R>
+static std::vector<Tw<R>> twiddles(int n) {
+  std::vector<Tw<R>> w(n);
+  for (int k = 0; k < n; ++k) {
+    const long double a = -2.0L * 3.14159265358979323846264338327950288L * k / n;
+    const long double cl = std::cos(a), sl = std::sin(a);
+    const R c = (R)cl, s = (R)sl;
+    const bool split = sizeof(R) == 4;
+    w[k] = {c, s, split ? (R)(cl - (long double)c) : (R)0, split ? (R)(sl - (long double)s) : (R)0};
+  }
+  return w;
+}
+
+static double fftfreq(int i, int n, double d) {
+  const int m = (i < (n + 1) / 2) ? i : i - n;
+  return (double)m / ((double)n * d);
+}
+
+// exp(2 i pi^2 q^2 dz / k) for q = fftfreq(n, d); optional extra real factor.
+static std::vector<double> prop_factor(int n, double d, double dz, double k, double extra) {
+  std::vector<double> out(2 * n);
+  for (int i = 0; i < n; ++i) {
+    const double q = fftfreq(i, n, d);
+    const double th = 2.0 * M_PI * M_PI * q * q * dz / k;
+    out[2 * i] = extra * std::cos(th);
+    out[2 * i + 1] = extra * std::sin(th);
+  }
+  return out;
+}
+
+static int upload(void** dst, const void* src, size_t bytes) {
+  hipError_t e = hipMalloc(dst, bytes);
+  if (e != hipSuccess) {
+    *dst = nullptr;
+    return hip_fail(e, "hipMalloc(plan table)");
+  }
+  e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(plan table)");
+  return SHG_OK;
+}
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+static bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+static bool pow2_in_range(int v) { return v >= 16 && v <= 512 && (v & (v - 1)) == 0; }
+
+int validate_params(const shg_params* p) {
+  if (!pow2_in_range(p->nx) || !pow2_in_range(p->ny))
+    return fail(SHG_EINVAL, "nx=%d ny=%d: each must be a power of two in [16, 512]", p->nx, p->ny);
+  if (p->nz < 1) return fail(SHG_EINVAL, "nz=%d must be >= 1", p->nz);
+  if (!finite_pos(p->lx) || !finite_pos(p->ly) || !finite_pos(p->lcr))
+    return fail(SHG_EINVAL, "lx, ly, lcr must be finite and positive");
+  if (!finite_pos(p->lambda_f) || !finite_pos(p->n_f) || !finite_pos(p->n_sh))
+    return fail(SHG_EINVAL, "lambda_f, n_f, n_sh must be finite and positive");
+  if (!std::isfinite(p->d_eff)) return fail(SHG_EINVAL, "d_eff must be finite");
+  if (!finite_nonneg(p->alpha_f) || !finite_nonneg(p->alpha_sh) || !finite_nonneg(p->beta_f) ||
+      !finite_nonneg(p->beta_sh))
+    return fail(SHG_EINVAL, "absorption coefficients must be finite and >= 0");
+  if (!std::isfinite(p->dk0) || !std::isfinite(p->ddk_dT) || !std::isfinite(p->dn_dT) ||
+      !std::isfinite(p->t_ref))
+    return fail(SHG_EINVAL, "dk0, ddk_dT, dn_dT, t_ref must be finite");
+  if (p->checkpoint_every < 0) return fail(SHG_EINVAL, "checkpoint_every must be >= 0");
+  if (p->flags & ~(uint32_t)(SHG_UNDEPLETED | SHG_NO_GRAPH))
+    return fail(SHG_EINVAL, "unknown flag bits 0x%x", p->flags);
+  return SHG_OK;
+}
+
+static constexpr double kEps0 = 8.8541878128e-12;
+static constexpr double kC = 299792458.0;
+
+int build_plan(Plan& pl) {
+  const shg_params& p = pl.p;
+  const double lam_f = p.lambda_f, lam_sh = lam_f / 2.0;
+  pl.dx = p.lx / p.nx;
+  pl.dy = p.ly / p.ny;
+  pl.dz = p.lcr / p.nz;
+  pl.k_f = 2.0 * M_PI * p.n_f / lam_f;
+  pl.k_sh = 2.0 * M_PI * p.n_sh / lam_sh;
+  pl.kappa_f = 2.0 * M_PI * p.d_eff / (p.n_f * lam_f);
+  pl.kappa_sh = 2.0 * M_PI * p.d_eff / (p.n_sh * lam_f);
+  pl.tpa_f = p.beta_f * kEps0 * kC * p.n_f / 2.0;
+  pl.tpa_sh = p.beta_sh * kEps0 * kC * p.n_sh / 2.0;
+  pl.lens_f = 2.0 * M_PI * p.dn_dT / lam_f;
+  pl.lens_sh = 2.0 * M_PI * p.dn_dT / lam_sh;
+  pl.pscale_f = kEps0 * kC * p.n_f / 2.0 * pl.dx * pl.dy;
+  pl.pscale_sh = kEps0 * kC * p.n_sh / 2.0 * pl.dx * pl.dy;
+  pl.ckpt = p.checkpoint_every > 0 ? p.checkpoint_every : 32;
+  pl.real_bytes = pl.dtype == SHG_C64 ? 4 : 8;
+  int rc;
+  if (pl.dtype == SHG_C64) {
+    auto tx = twiddles<float>(p.nx), ty = twiddles<float>(p.ny);
+    if ((rc = upload(&pl.tw_x, tx.data(), tx.size() * sizeof(tx[0])))) return rc;
+    if ((rc = upload(&pl.tw_y, ty.data(), ty.size() * sizeof(ty[0])))) return rc;
+  } else {
+    auto tx = twiddles<double>(p.nx), ty = twiddles<double>(p.ny);
+    if ((rc = upload(&pl.tw_x, tx.data(), tx.size() * sizeof(tx[0])))) return rc;
+    if ((rc = upload(&pl.tw_y, ty.data(), ty.size() * sizeof(ty[0])))) return rc;
+  }
+  const double norm = 1.0 / ((double)p.nx * (double)p.ny);
+  const double ks[2] = {pl.k_f, pl.k_sh};
+  const double al[2] = {p.alpha_f, p.alpha_sh};
+  for (int w = 0; w < 2; ++w) {
+    auto mx = prop_factor(p.nx, pl.dx, pl.dz, ks[w], 1.0);
+    auto my = prop_factor(p.ny, pl.dy, pl.dz, ks[w], std::exp(-al[w] * pl.dz / 2.0) * norm);
+    if ((rc = upload((void**)&pl.mx[w], mx.data(), mx.size() * sizeof(double)))) return rc;
+    if ((rc = upload((void**)&pl.my[w], my.data(), my.size() * sizeof(double)))) return rc;
+  }
+  default_schedule(pl);
+  if (pl.row_e == 0 || pl.col_e == 0)
+    return fail(SHG_EUNSUPPORTED, "no built schedule for nx=%d ny=%d", p.nx, p.ny);
+  return SHG_OK;
+}
+
+void free_timing(Plan& pl) {
+  for (hipEvent_t e : pl.ev_pool) (void)hipEventDestroy(e);
+  pl.ev_pool.clear();
+  pl.ev_kind.clear();
+  pl.ev_used = 0;
+}
+
+void free_plan_tables(Plan& pl) {
+  free_timing(pl);
+  if (pl.gexec) (void)hipGraphExecDestroy(pl.gexec);
+  pl.gexec = nullptr;
+  if (pl.cap_stream) (void)hipStreamDestroy(pl.cap_stream);
+  pl.cap_stream = nullptr;
+  void* ptrs[] = {pl.tw_x, pl.tw_y, pl.mx[0], pl.mx[1], pl.my[0], pl.my[1], pl.own_ws,
+                  pl.batch_ws};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  pl.tw_x = pl.tw_y = nullptr;
+  pl.mx[0] = pl.mx[1] = pl.my[0] = pl.my[1] = nullptr;
+  pl.own_ws = nullptr;
+  pl.batch_ws = nullptr;
+  free_adjoint(pl);
+}
+
+// ---------------------------------------------------------------- forward
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t forward_ws_bytes(const Plan& pl) {
+  const size_t phase = (size_t)pl.p.nz * 5 * 2 * pl.real_bytes;
+  const size_t parts = (size_t)pl.p.ny * 2 * sizeof(double);
+  return align256(phase) + align256(parts);
+}
+
+template <typename R>
+static int enqueue_forward_t(Plan& pl, cx<R>* a, cx<R>* b, const double* dk_z, int s0, int s1,
+                             char* ws, double* powers, hipStream_t st) {
+  const shg_params& p = pl.p;
+  cx<R>* phase = (cx<R>*)ws;
+  double* partials = (double*)(ws + align256((size_t)p.nz * 5 * sizeof(cx<R>)));
+  hipLaunchKernelGGL((phase_table<R>), dim3(1), dim3(256), 0, st, dk_z, p.dk0, p.nz, pl.dz,
+                     phase);
+  RowArgs<R> ra{};
+  ra.a = a;
+  ra.b = b;
+  ra.tw = (const Tw<R>*)pl.tw_x;
+  ra.phase = phase;
+  ra.ny = p.ny;
+  ra.kf = (R)pl.kappa_f;
+  ra.ks = (R)pl.kappa_sh;
+  ra.tf = (R)(pl.tpa_f / 2.0);
+  ra.ts = (R)(pl.tpa_sh / 2.0);
+  ra.h = (R)(pl.dz / 2.0);
+  ra.undepleted = (p.flags & SHG_UNDEPLETED) ? 1 : 0;
+  ColArgs<R> ca{};
+  ca.f[0] = a;
+  ca.f[1] = b;
+  ca.tw = (const Tw<R>*)pl.tw_y;
+  for (int w = 0; w < 2; ++w) {
+    ca.mx[w] = pl.mx[w];
+    ca.my[w] = pl.my[w];
+  }
+  ca.nx = p.nx;
+  ca.tiles = p.nx / pl.col_tc;
+  int rows = 1;
+  LaunchTimer tm{&pl};
+  // first row pass: N(dz/2) of step s0, then FFT_x
+  ra.s_second = -1;
+  ra.s_first = s0;
+  ra.inv_in = 0;
+  ra.fwd_out = 1;
+  ra.partials = nullptr;
+  if (!row_dispatch<R>(p.nx, pl.row_e, pl.row_wg, &ra, st, &rows, &tm))
+    return fail(SHG_EUNSUPPORTED, "row schedule e=%d wg=%d not built", pl.row_e, pl.row_wg);
+  for (int s = s0; s < s1; ++s) {
+    if (!col_dispatch<R>(p.ny, pl.col_e, pl.col_tc, &ca, st, &tm))
+      return fail(SHG_EUNSUPPORTED, "column schedule e=%d tc=%d not built", pl.col_e, pl.col_tc);
+    const bool last = (s == s1 - 1);
+    ra.s_second = s;
+    ra.s_first = last ? -1 : s + 1;
+    ra.inv_in = 1;
+    ra.fwd_out = last ? 0 : 1;
+    ra.partials = (last && powers) ? partials : nullptr;
+    row_dispatch<R>(p.nx, pl.row_e, pl.row_wg, &ra, st, &rows, &tm);
+  }
+  if (powers) {
+    hipLaunchKernelGGL(power_finalize, dim3(1), dim3(256), 0, st, (const double*)partials,
+                       p.ny / rows, pl.pscale_f, pl.pscale_sh, powers);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return SHG_OK;
+}
+
+int enqueue_forward(Plan& pl, void* a, void* b, const double* dk_z, int s0, int s1, void* ws,
+                    double* powers, hipStream_t st) {
+  if (pl.dtype == SHG_C64)
+    return enqueue_forward_t<float>(pl, (cx<float>*)a, (cx<float>*)b, dk_z, s0, s1, (char*)ws,
+                                    powers, st);
+  return enqueue_forward_t<double>(pl, (cx<double>*)a, (cx<double>*)b, dk_z, s0, s1, (char*)ws,
+                                   powers, st);
+}
+
+int ensure_own_ws(Plan& pl, size_t bytes) {
+  if (pl.own_ws && pl.own_ws_bytes >= bytes) return SHG_OK;
+  if (pl.own_ws) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    (void)hipFree(pl.own_ws);
+    pl.own_ws = nullptr;
+  }
+  hipError_t e = hipMalloc(&pl.own_ws, bytes);
+  if (e != hipSuccess) {
+    pl.own_ws = nullptr;
+    return hip_fail(e, "hipMalloc(workspace)");
+  }
+  pl.own_ws_bytes = bytes;
+  return SHG_OK;
+}
+
+// Replays a cached graph of the whole launch sequence when the arguments are
+// the same as last time; otherwise captures a new one on a private stream.
+static int run_forward(Plan& pl, void* a, void* b, const double* dk_z, int s0, int s1, void* ws,
+                       double* powers, hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(st, &cs);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+  const bool use_graph = !(pl.p.flags & SHG_NO_GRAPH) && !pl.timing &&
+                         cs == hipStreamCaptureStatusNone && (s1 - s0) >= 2;
+  if (!use_graph) return enqueue_forward(pl, a, b, dk_z, s0, s1, ws, powers, st);
+  GraphKey key{a, b, dk_z, ws, powers, s0, s1, pl.row_e, pl.row_wg, pl.col_e, pl.col_tc};
+  if (!pl.gexec || !(key == pl.gkey)) {
+    if (pl.gexec) {
+      (void)hipGraphExecDestroy(pl.gexec);
+      pl.gexec = nullptr;
+    }
+    if (!pl.cap_stream) {
+      e = hipStreamCreateWithFlags(&pl.cap_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    }
+    e = hipStreamBeginCapture(pl.cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    int rc = enqueue_forward(pl, a, b, dk_z, s0, s1, ws, powers, pl.cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(pl.cap_stream, &g);
+    if (rc != SHG_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&pl.gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      pl.gexec = nullptr;
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    pl.gkey = key;
+  }
+  e = hipGraphLaunch(pl.gexec, st);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return SHG_OK;
+}
+
+int check_plan(const shg_plan* plan) {
+  if (!plan) return fail(SHG_ESTATE, "plan is NULL");
+  const Plan* pl = reinterpret_cast<const Plan*>(plan);
+  if (pl->magic != Plan::kMagic) return fail(SHG_ESTATE, "plan is not live (destroyed or invalid)");
+  return SHG_OK;
+}
+
+int sticky_device_error() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "earlier HIP error");
+  return SHG_OK;
+}
+
+int propagate(Plan& pl, void* a_f, void* a_sh, const double* dk_z, const void* temp, int s0,
+              int s1, void* ws, double* powers, hipStream_t st) {
+  if (!a_f || !a_sh) return fail(SHG_EINVAL, "a_f and a_sh must be non-NULL device pointers");
+  if (!(0 <= s0 && s0 < s1 && s1 <= pl.p.nz))
+    return fail(SHG_EINVAL, "step range [%d, %d) not within [0, nz=%d]", s0, s1, pl.p.nz);
+  if (temp) return propagate_temp(pl, a_f, a_sh, dk_z, temp, s0, s1, ws, powers, st);
+  int rc = sticky_device_error();
+  if (rc) return rc;
+  if (!ws) {
+    if ((rc = ensure_own_ws(pl, forward_ws_bytes(pl)))) return rc;
+    ws = pl.own_ws;
+  }
+  return run_forward(pl, a_f, a_sh, dk_z, s0, s1, ws, powers, st);
+}
+
+}  // namespace shg
+
+using namespace shg;
+
+extern "C" {
+
+int shg_plan_create(shg_plan** out, const shg_params* p, shg_dtype dtype) {
+  if (!out) return fail(SHG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!p) return fail(SHG_EINVAL, "params is NULL");
+  if (dtype != SHG_C64 && dtype != SHG_C128) return fail(SHG_EINVAL, "unknown dtype %d", (int)dtype);
+  int rc = validate_params(p);
+  if (rc) return rc;
+  Plan* pl = new (std::nothrow) Plan();
+  if (!pl) return fail(SHG_ENOMEM, "host allocation failed");
+  pl->p = *p;
+  pl->dtype = dtype;
+  (void)hipGetDevice(&pl->device);
+  rc = build_plan(*pl);
+  if (rc) {
+    std::string msg = g_last_error;
+    free_plan_tables(*pl);
+    delete pl;
+    g_last_error = msg;
+    return rc;
+  }
+  pl->magic = Plan::kMagic;
+  *out = reinterpret_cast<shg_plan*>(pl);
+  return ok();
+}
+
+int shg_plan_destroy(shg_plan* plan) {
+  if (!plan) return ok();
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  Plan* pl = reinterpret_cast<Plan*>(plan);
+  free_plan_tables(*pl);
+  pl->magic = 0;
+  delete pl;
+  return ok();
+}
+
+size_t shg_workspace_bytes(const shg_plan* plan, int for_adjoint) {
+  if (check_plan(plan)) return 0;
+  const Plan* pl = reinterpret_cast<const Plan*>(plan);
+  return for_adjoint ? adjoint_ws_bytes(*pl) : forward_ws_bytes(*pl);
+}
+
+int shg_propagate(shg_plan* plan, void* a_f, void* a_sh, const double* dk_z, const void* temp,
+                  int32_t s_begin, int32_t s_end, void* workspace, double* powers, void* stream) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  Plan* pl = reinterpret_cast<Plan*>(plan);
+  rc = propagate(*pl, a_f, a_sh, dk_z, temp, s_begin, s_end, workspace, powers,
+                 (hipStream_t)stream);
+  return rc ? rc : ok();
+}
+
+int shg_plan_set_schedule(shg_plan* plan, int32_t row_e, int32_t row_wg, int32_t col_e,
+                          int32_t col_tc) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  Plan* pl = reinterpret_cast<Plan*>(plan);
+  const int re = row_e ? row_e : pl->row_e, rw = row_wg ? row_wg : pl->row_wg;
+  const int ce = col_e ? col_e : pl->col_e, ct = col_tc ? col_tc : pl->col_tc;
+  int rows = 0;
+  if (!row_supported(*pl, re, rw, &rows))
+    return fail(SHG_EUNSUPPORTED, "row schedule e=%d wg=%d not built for nx=%d ny=%d", re, rw,
+                pl->p.nx, pl->p.ny);
+  if (!col_supported(*pl, ce, ct))
+    return fail(SHG_EUNSUPPORTED, "column schedule e=%d tc=%d not built for nx=%d ny=%d", ce, ct,
+                pl->p.nx, pl->p.ny);
+  pl->row_e = re;
+  pl->row_wg = rw;
+  pl->row_rows = rows;
+  pl->col_e = ce;
+  pl->col_tc = ct;
+  return ok();
+}
+
+int shg_plan_describe(const shg_plan* plan, char* buf, size_t len) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  const Plan* pl = reinterpret_cast<const Plan*>(plan);
+  if (buf && len) {
+    snprintf(buf, len,
+             "dtype=%s nx=%d ny=%d nz=%d row(e=%d wg=%d rows=%d) col(e=%d tc=%d) graph=%d",
+             pl->dtype == SHG_C64 ? "c64" : "c128", pl->p.nx, pl->p.ny, pl->p.nz, pl->row_e,
+             pl->row_wg, pl->row_rows, pl->col_e, pl->col_tc,
+             (pl->p.flags & SHG_NO_GRAPH) ? 0 : 1);
+  }
+  return ok();
+}
+
+int shg_plan_set_timing(shg_plan* plan, int32_t enable) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  Plan* pl = reinterpret_cast<Plan*>(plan);
+  pl->timing = enable ? 1 : 0;
+  pl->ev_used = 0;
+  return ok();
+}
+
+int shg_plan_kernel_times(shg_plan* plan, double* out) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!out) return fail(SHG_EINVAL, "out is NULL");
+  Plan* pl = reinterpret_cast<Plan*>(plan);
+  double sum[2] = {0.0, 0.0}, cnt[2] = {0.0, 0.0};
+  for (size_t i = 0; i < pl->ev_used; ++i) {
+    hipError_t e = hipEventSynchronize(pl->ev_pool[2 * i + 1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, pl->ev_pool[2 * i], pl->ev_pool[2 * i + 1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    const int k = pl->ev_kind[i] ? 1 : 0;
+    sum[k] += ms;
+    cnt[k] += 1.0;
+  }
+  out[0] = sum[0];
+  out[1] = cnt[0];
+  out[2] = sum[1];
+  out[3] = cnt[1];
+  pl->ev_used = 0;
+  return ok();
+}
+
+const char* shg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

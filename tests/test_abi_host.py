@@ -1,0 +1,150 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load on a machine without a GPU, export every entry point
+that include/shg.h declares, agree with the binding on the parameter struct
+layout, and reject invalid arguments with the documented codes before it
+touches the device.
+"""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2410_04994_amd import binding
+from paper_2410_04994_amd.binding import ShgParams, make_params
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "shg.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(shg_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return binding.load_library()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert "shg_propagate" in names and "shg_propagate_adjoint" in names
+    assert "shg_propagate_batch" in names and "shg_plan_create" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_params_struct_layout_matches_c():
+    fields = [f for f, _ in ShgParams._fields_]
+    prog = ["#include <stdio.h>", "#include <stddef.h>", '#include "shg.h"', "int main(void){",
+            'printf("%zu\\n", sizeof(shg_params));']
+    prog += [f'printf("%zu\\n", offsetof(shg_params, {f}));' for f in fields]
+    prog += ["return 0;}"]
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(c, "w").write("\n".join(prog))
+        subprocess.run(["gcc", "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
+        out = [int(v) for v in subprocess.run([exe], capture_output=True, text=True,
+                                              check=True).stdout.split()]
+    assert out[0] == ctypes.sizeof(ShgParams)
+    for f, off in zip(fields, out[1:]):
+        assert getattr(ShgParams, f).offset == off, f
+
+
+def good_params(**kw):
+    p = dict(nx=64, ny=32, nz=10, lx=1e-3, ly=1e-3, lcr=1e-2, lambda_f=1.064e-6, n_f=2.14,
+             n_sh=2.18, d_eff=1e-11, alpha_f=0.0, alpha_sh=0.0, beta_f=0.0, beta_sh=0.0, dk0=0.0,
+             ddk_dT=0.0, dn_dT=0.0, t_ref=0.0)
+    p.update(kw)
+    return p
+
+
+def create(lib, p, dtype=0, flags=0):
+    h = ctypes.c_void_p()
+    cp = make_params(p, flags)
+    rc = lib.shg_plan_create(ctypes.byref(h), ctypes.byref(cp), dtype)
+    return rc, h, lib.shg_last_error().decode()
+
+
+@pytest.mark.parametrize("bad,needle", [
+    (dict(nx=63), "power of two"), (dict(ny=1024), "power of two"), (dict(nx=8), "power of two"),
+    (dict(nz=0), "nz"), (dict(lx=-1.0), "lx"), (dict(lcr=float("nan")), "lcr"),
+    (dict(n_sh=0.0), "n_sh"), (dict(alpha_f=-1.0), "absorption"),
+    (dict(beta_sh=float("inf")), "absorption"), (dict(dk0=float("nan")), "dk0"),
+    (dict(d_eff=float("inf")), "d_eff"),
+])
+def test_invalid_params_rejected_before_device(lib, bad, needle):
+    rc, h, msg = create(lib, good_params(**bad))
+    assert rc == binding.SHG_EINVAL
+    assert h.value is None
+    assert needle in msg
+
+
+def test_unknown_flags_and_dtype(lib):
+    rc, _, msg = create(lib, good_params(), flags=1 << 7)
+    assert rc == binding.SHG_EINVAL and "flag" in msg
+    rc, _, msg = create(lib, good_params(), dtype=7)
+    assert rc == binding.SHG_EINVAL and "dtype" in msg
+    cp = make_params(good_params())
+    assert lib.shg_plan_create(None, ctypes.byref(cp), 0) == binding.SHG_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.shg_plan_create(ctypes.byref(h), None, 0) == binding.SHG_EINVAL
+
+
+def test_null_and_dead_plans(lib):
+    assert lib.shg_plan_destroy(None) == binding.SHG_OK
+    assert lib.shg_workspace_bytes(None, 0) == 0
+    rc = lib.shg_propagate(None, None, None, None, None, 0, 1, None, None, None)
+    assert rc == binding.SHG_ESTATE
+    assert "NULL" in lib.shg_last_error().decode()
+    buf = ctypes.create_string_buffer(64)
+    assert lib.shg_plan_describe(None, buf, 64) == binding.SHG_ESTATE
+    assert lib.shg_plan_set_schedule(None, 0, 0, 0, 0) == binding.SHG_ESTATE
+    rc = lib.shg_propagate_batch(0, None, None, None, None, None, None, None)
+    assert rc == binding.SHG_EINVAL
+    # a random pointer that is not a plan is rejected, not dereferenced as one
+    junk = (ctypes.c_uint64 * 64)()
+    assert lib.shg_propagate(ctypes.cast(junk, ctypes.c_void_p), None, None, None, None, 0, 1,
+                             None, None, None) == binding.SHG_ESTATE
+
+
+def test_valid_params_reach_the_device_and_fail_cleanly_without_one(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rc, h, msg = create(lib, good_params())
+    assert rc in (binding.SHG_EDEVICE, binding.SHG_ENOMEM)
+    assert h.value is None and msg
+
+
+def test_binding_refuses_missing_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(binding, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        binding.load_library(str(tmp_path / "nope.so"))
+
+
+def test_binding_refuses_host_tensors():
+    import torch
+    with pytest.raises(ValueError, match="CUDA"):
+        binding._ptr(torch.zeros(4, dtype=torch.complex64), "a_f")
+
+
+def test_workload_inputs_are_seeded():
+    import workloads
+    w = workloads.c2_plain_c64()
+    a, b = workloads.phase_noise(w), workloads.phase_noise(w)
+    assert np.array_equal(a, b) and a.shape == (256, 256)
+    assert abs(a.std() - 0.01) < 2e-4
+    assert abs(w.w0 - 28.912e-6) < 1e-9 and abs(w.dk0 + 108.548) < 1e-3
+    batch = workloads.c3_batch()
+    sizes = [x.nx for x in batch]
+    assert len(batch) == 512 and sizes.count(64) == 128 and sizes.count(256) == 128
+    assert all(200 <= x.nz <= 1000 and 0.5 <= x.xi <= 5.0 for x in batch)
+    assert [x.nz for x in workloads.c3_batch()] == [x.nz for x in batch]

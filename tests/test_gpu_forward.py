@@ -1,0 +1,167 @@
+"""Parity of the HIP forward march with the FP64 oracle (needs the GPU).
+
+Tolerances: complex64 path field relative L2 <= 1e-4 and efficiency / power
+relative error <= 1e-5; complex128 path (same kernels in FP64) <= 1e-12.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import beams, ssfm
+from gpu_util import inputs, run_gpu, run_oracle, compare, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def make_plan(wl, dtype="c64", **kw):
+    from paper_2410_04994_amd import Plan
+    return Plan(wl.params(), dtype, **kw)
+
+
+def parity(wl, dtype="c64", label="", dk_z=None, sched=None, flags=0):
+    plan = make_plan(wl, dtype, flags=flags)
+    if sched:
+        plan.set_schedule(*sched)
+    a0, b0 = inputs(wl, dtype)
+    gpu = run_gpu(plan, a0, b0, dk_z=dk_z)
+    ref = run_oracle(wl, a0, b0, dk_z=dk_z)
+    return compare(wl, gpu, ref, dtype, label or plan.describe())
+
+
+def test_config1_complex128_algorithmic_parity():
+    """64x64 x 200 steps, 4 w0 window, FP64: the kernels compute the oracle's scheme."""
+    parity(workloads.c1_plain_fp64(), "c128")
+
+
+def test_config1_complex64():
+    parity(workloads.c1_plain_fp64().with_(dtype="c64"), "c64")
+
+
+def test_config2_physics_small_grid():
+    """Depleted pump, linear + two-photon absorption, dk at the optimum, phase noise."""
+    parity(workloads.c2_plain_c64().with_(nx=64, ny=64, nz=120), "c64")
+
+
+def test_config2_full_size():
+    """256x256 x 1000 steps, 30 W, xi = 2.84, with the default (benchmarked) schedule."""
+    ef, es, epf, eps = parity(workloads.c2_plain_c64(), "c64")
+    assert es < 5e-5 and eps < 5e-6
+
+
+def test_config2_full_grid_complex128():
+    parity(workloads.c2_plain_c64().with_(nz=40), "c128")
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(16, 16, 9), (512, 16, 3), (16, 512, 3), (128, 32, 7),
+                                      (32, 256, 5), (512, 512, 2)])
+def test_grid_shapes(nx, ny, nz):
+    base = workloads.c2_plain_c64()
+    wl = base.with_(nx=nx, ny=ny, nz=nz, lx=base.lx * nx / 256, ly=base.ly * ny / 256)
+    parity(wl, "c64")
+    parity(wl.with_(nz=2), "c128")
+
+
+def test_single_step():
+    parity(workloads.c2_plain_c64().with_(nx=64, ny=64, nz=1), "c64")
+    parity(workloads.c2_plain_c64().with_(nx=64, ny=64, nz=1), "c128")
+
+
+def test_undepleted_pump():
+    wl = workloads.c2_plain_c64().with_(nx=64, ny=64, nz=60, undepleted=True)
+    parity(wl, "c64")
+    parity(wl, "c128")
+
+
+def test_per_step_mismatch_profile():
+    wl = workloads.c4_diff_c64().with_(nx=64, ny=64, nz=80)
+    rng = np.random.Generator(np.random.PCG64(12))
+    dk = wl.dk0 + 300.0 * rng.normal(size=wl.nz)
+    parity(wl, "c64", dk_z=dk)
+    parity(wl, "c128", dk_z=dk)
+
+
+def test_step_ranges_resume_bitwise():
+    wl = workloads.c2_plain_c64().with_(nx=64, ny=64, nz=30)
+    plan = make_plan(wl)
+    a0, b0 = inputs(wl)
+    full = run_gpu(plan, a0, b0)
+    part = run_gpu(plan, a0, b0, s_end=11)
+    rest = run_gpu(plan, part[0], part[1], s_begin=11)
+    assert np.array_equal(rest[0], full[0]) and np.array_equal(rest[1], full[1])
+    ref = run_oracle(wl, a0, b0, s_end=11)
+    assert rel(part[1], ref["a_sh"]) < 1e-4
+
+
+def test_graph_replay_equals_plain_launches_and_is_deterministic():
+    from paper_2410_04994_amd import SHG_NO_GRAPH
+    wl = workloads.c2_plain_c64().with_(nx=128, ny=128, nz=25)
+    a0, b0 = inputs(wl)
+    g = make_plan(wl)
+    r1 = run_gpu(g, a0, b0)
+    r2 = run_gpu(g, a0, b0)       # replays the cached graph
+    s = run_gpu(make_plan(wl, flags=SHG_NO_GRAPH), a0, b0)
+    for x, y in ((r1, r2), (r1, s)):
+        assert all(np.array_equal(u, v) for u, v in zip(x, y))
+
+
+def test_every_built_schedule_matches_the_oracle():
+    wl = workloads.c2_plain_c64().with_(nx=256, ny=256, nz=6)
+    plan = make_plan(wl)
+    a0, b0 = inputs(wl)
+    ref = run_oracle(wl, a0, b0)
+    tried = 0
+    for re_ in (4, 8, 16):
+        for rw in (64, 256):
+            for ce in (4, 8, 16):
+                for ct in (1, 2, 4, 8, 16):
+                    try:
+                        plan.set_schedule(re_, rw, ce, ct)
+                    except Exception:
+                        continue
+                    compare(wl, run_gpu(plan, a0, b0), ref, "c64", plan.describe())
+                    tried += 1
+    assert tried >= 10
+
+
+def test_invalid_step_range_and_fields():
+    from paper_2410_04994_amd import ShgError
+    wl = workloads.c2_plain_c64().with_(nx=64, ny=64, nz=10)
+    plan = make_plan(wl)
+    a = torch.zeros((64, 64), dtype=torch.complex64, device="cuda")
+    b = torch.zeros_like(a)
+    for s0, s1 in ((0, 11), (5, 5), (-1, 3), (7, 2)):
+        with pytest.raises(ShgError, match="SHG_EINVAL"):
+            plan.propagate(a, b, s_begin=s0, s_end=s1)
+    with pytest.raises(ValueError):
+        plan.propagate(a.to(torch.complex128), b)
+
+
+def test_explicit_workspace_and_no_powers():
+    wl = workloads.c2_plain_c64().with_(nx=64, ny=64, nz=12)
+    plan = make_plan(wl)
+    a0, b0 = inputs(wl)
+    ws = torch.empty(plan.workspace_bytes(), dtype=torch.uint8, device="cuda")
+    a = torch.from_numpy(a0).cuda()
+    b = torch.from_numpy(b0).cuda()
+    pw = plan.propagate(a, b, workspace=ws)
+    ref = run_oracle(wl, a0, b0)
+    compare(wl, (a.cpu().numpy(), b.cpu().numpy(), pw.cpu().numpy()), ref)
+
+
+def test_gpu_beam_builder_matches_oracle_builder():
+    from paper_2410_04994_amd import beams as gb
+    wl = workloads.c2_plain_c64()
+    th = workloads.phase_noise(wl)
+    g = gb.pump_for(wl, theta=torch.from_numpy(th).cuda(), dtype=torch.complex128).cpu().numpy()
+    o = beams.input_pump(wl.params(), wl.power, wl.w0, wl.focus, th)
+    assert rel(g, o) < 1e-12
+    c = ssfm.coefficients(wl.params())
+    assert abs(ssfm.power(g, wl.n_f, c.dx, c.dy) / wl.power - 1) < 1e-6
