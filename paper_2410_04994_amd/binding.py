@@ -248,7 +248,7 @@ def propagate_batch(plans: Sequence[Plan], a_f: Sequence, a_sh: Sequence, dk_z: 
     """March every instance over its whole crystal; returns [n, 2] powers."""
     torch = _torch()
     n = len(plans)
-    if powers is None:
+    if powers is None and n > 0:
         powers = torch.empty((n, 2), dtype=torch.float64, device=a_f[0].device)
     hp = (_VP * n)(*[p.handle for p in plans])
     fa = (_VP * n)(*[p._field(t, "a_f[i]") for p, t in zip(plans, a_f)])

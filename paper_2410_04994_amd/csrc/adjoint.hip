@@ -1,0 +1,326 @@
+// shg_propagate_adjoint: checkpointed reverse march.
+//
+// Forward sweep: the march runs in segments of K steps; the real-space state at
+// the start of every segment is kept (checkpoints).  Backward sweep, segment by
+// segment from the exit: the segment is recomputed from its checkpoint with the
+// row passes staging, for every step s, the real-space state u_s that enters the
+// second half-step; then the adjoint passes run in reverse order
+//   row_adj(top: second half of e-1), [col_adj(s), row_adj(first half of s,
+//   second half of s-1)] for s = e-1 .. b+1, col_adj(b), row_adj(first half of b)
+// and leave the cotangent of the segment's start state in real space.
+#include <hip/hip_runtime.h>
+
+#include "adjoint_kernels.hpp"
+#include "plan.hpp"
+
+namespace shg {
+
+template <typename R, int N, int E, int WG>
+constexpr bool adj_valid() {
+  if constexpr (E > N) return false;
+  constexpr int G = N / E;
+  constexpr int rows = RowShape<G, WG>::rows;
+  constexpr size_t lds = (size_t)rows * 4 * padded_len<N>() * sizeof(cx<R>);
+  if (G * rows > 1024 || lds > 64 * 1024) return false;
+  if constexpr (sizeof(R) == 8) return (E == 4 || E == 8) && WG == 64;
+  return true;
+}
+
+template <typename R, int N, int E, int WG>
+bool adj_try(int e, int wg, const RowAdjArgs<R>* a, const RowAdjTArgs<R>* q, hipStream_t st,
+             int* rows_out) {
+  if constexpr (adj_valid<R, N, E, WG>()) {
+    if (e != E || wg != WG) return false;
+    constexpr int G = N / E;
+    using S = RowShape<G, WG>;
+    if (rows_out) *rows_out = S::rows;
+    if (a && q) {
+      hipLaunchKernelGGL((row_adj_pass_t<R, N, G, S::rows>), dim3(a->ny / S::rows),
+                         dim3(S::threads), 0, st, *a, *q);
+    } else if (a) {
+      hipLaunchKernelGGL((row_adj_pass<R, N, G, S::rows>), dim3(a->ny / S::rows),
+                         dim3(S::threads), 0, st, *a);
+    }
+    return true;
+  } else {
+    (void)e; (void)wg; (void)a; (void)q; (void)st; (void)rows_out;
+    return false;
+  }
+}
+
+template <typename R, int N>
+bool adj_dispatch_n(int e, int wg, const RowAdjArgs<R>* a, const RowAdjTArgs<R>* q,
+                    hipStream_t st, int* rows) {
+  return adj_try<R, N, 4, 64>(e, wg, a, q, st, rows) ||
+         adj_try<R, N, 4, 256>(e, wg, a, q, st, rows) ||
+         adj_try<R, N, 8, 64>(e, wg, a, q, st, rows) ||
+         adj_try<R, N, 8, 256>(e, wg, a, q, st, rows) ||
+         adj_try<R, N, 16, 64>(e, wg, a, q, st, rows) ||
+         adj_try<R, N, 16, 256>(e, wg, a, q, st, rows);
+}
+
+template <typename R>
+bool adj_dispatch(int n, int e, int wg, const RowAdjArgs<R>* a, const RowAdjTArgs<R>* q,
+                  hipStream_t st, int* rows) {
+  switch (n) {
+    case 16: return adj_dispatch_n<R, 16>(e, wg, a, q, st, rows);
+    case 32: return adj_dispatch_n<R, 32>(e, wg, a, q, st, rows);
+    case 64: return adj_dispatch_n<R, 64>(e, wg, a, q, st, rows);
+    case 128: return adj_dispatch_n<R, 128>(e, wg, a, q, st, rows);
+    case 256: return adj_dispatch_n<R, 256>(e, wg, a, q, st, rows);
+    case 512: return adj_dispatch_n<R, 512>(e, wg, a, q, st, rows);
+    default: return false;
+  }
+}
+
+// Workspace layout of the adjoint (all offsets 256-byte aligned).
+struct AdjLayout {
+  size_t fwd, ckpt, work, stage, gp1, gp2, gh;
+  size_t psi_work, psi_ckpt, psi_stage, carry, moments;   // temperature field only
+  size_t total;
+  int segs, k, nblk;
+};
+
+static AdjLayout adj_layout(const Plan& pl) {
+  AdjLayout L{};
+  const size_t n2 = (size_t)pl.p.nx * pl.p.ny;
+  const size_t state = align256(2 * n2 * 2 * pl.real_bytes);   // both fields
+  L.k = pl.ckpt;
+  L.segs = (pl.p.nz + L.k - 1) / L.k;
+  int rows = 1;
+  L.nblk = pl.p.ny;   // upper bound on row-pass blocks
+  if (row_supported(pl, pl.row_e, pl.row_wg, &rows)) L.nblk = pl.p.ny / rows;
+  size_t off = 0;
+  L.fwd = off;
+  off += align256(forward_ws_bytes(pl));
+  L.ckpt = off;
+  off += state * (L.segs + 1);
+  L.work = off;
+  off += state;
+  L.stage = off;
+  off += state * L.k;
+  L.gp1 = off;
+  off += align256((size_t)pl.p.nz * L.nblk * 2 * sizeof(double));
+  L.gp2 = off;
+  off += align256((size_t)pl.p.nz * L.nblk * 2 * sizeof(double));
+  L.gh = off;
+  off += align256((size_t)pl.p.nz * 2 * sizeof(double));
+  const size_t rplane = align256(n2 * pl.real_bytes);
+  L.psi_work = off;
+  off += rplane;
+  L.psi_ckpt = off;
+  off += rplane * L.segs;
+  L.psi_stage = off;
+  off += rplane * L.k;
+  L.carry = off;
+  off += align256(n2 * 4 * pl.real_bytes);
+  L.moments = off;
+  off += align256(n2 * 2 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+size_t adjoint_ws_bytes(const Plan& pl) { return adj_layout(pl).total; }
+
+void free_adjoint(Plan&) {}
+
+template <typename R>
+static int adjoint_t(Plan& pl, const void* a_f_in, const void* a_sh_in, const double* dk_z,
+                     const void* temp, const void* g_f_out, const void* g_sh_out,
+                     const double* pw, void* g_f_in, void* g_sh_in, double* g_dk, double* g_t,
+                     void* a_f_out, void* a_sh_out, double* powers, char* ws, hipStream_t st) {
+  const shg_params& p = pl.p;
+  const AdjLayout L = adj_layout(pl);
+  const size_t n2 = (size_t)p.nx * p.ny;
+  const size_t state = align256(2 * n2 * sizeof(cx<R>));
+  auto ck = [&](int k) { return (cx<R>*)(ws + L.ckpt + state * k); };
+  cx<R>* work = (cx<R>*)(ws + L.work);
+  cx<R>* stage = (cx<R>*)(ws + L.stage);
+  double* gp1 = (double*)(ws + L.gp1);
+  double* gp2 = (double*)(ws + L.gp2);
+  double* gh = (double*)(ws + L.gh);
+  char* fws = ws + L.fwd;
+  cx<R>* fin_a = a_f_out ? (cx<R>*)a_f_out : ck(L.segs);
+  cx<R>* fin_b = a_sh_out ? (cx<R>*)a_sh_out : ck(L.segs) + n2;
+  auto seg_in = [&](int k, const void** a, const void** b) {
+    if (k == 0) {
+      *a = a_f_in;
+      *b = a_sh_in;
+    } else {
+      *a = ck(k);
+      *b = ck(k) + n2;
+    }
+  };
+  int rc;
+  const bool th = temp != nullptr;
+  R* psi_work = (R*)(ws + L.psi_work);
+  const size_t rplane = align256(n2 * sizeof(R));
+  auto psi_ck = [&](int k) { return (R*)(ws + L.psi_ckpt + rplane * k); };
+  R* psi_stage = (R*)(ws + L.psi_stage);
+  Carry<R>* carry = (Carry<R>*)(ws + L.carry);
+  double* moments = (double*)(ws + L.moments);
+  const unsigned nb = (unsigned)((n2 + 255) / 256);
+  if (th) {
+    hipLaunchKernelGGL((psi_init<R>), dim3(nb), dim3(256), 0, st, (const R*)temp, 0, p.t_ref,
+                       pl.dz, psi_work, n2);
+  }
+  // ---- forward sweep with checkpoints
+  for (int k = 0; k < L.segs; ++k) {
+    const int b = k * L.k, e = std::min(p.nz, b + L.k);
+    const void *ia, *ib;
+    seg_in(k, &ia, &ib);
+    const bool last = (k == L.segs - 1);
+    FwdIO io{ia, ib, work, work + n2, last ? (void*)fin_a : (void*)ck(k + 1),
+             last ? (void*)fin_b : (void*)(ck(k + 1) + n2), nullptr};
+    if (th) {
+      hipLaunchKernelGGL((copy_real<R>), dim3(nb), dim3(256), 0, st, (const R*)psi_work,
+                         psi_ck(k), n2);
+      io.temp = temp;
+      io.psi = psi_work;
+    }
+    rc = enqueue_forward_io(pl, io, dk_z, b, e, fws, last ? powers : nullptr, st, k == 0);
+    if (rc) return rc;
+  }
+  // ---- cotangent of the exit fields
+  cx<R>* la = (cx<R>*)g_f_in;
+  cx<R>* lb = (cx<R>*)g_sh_in;
+  hipLaunchKernelGGL((adjoint_seed<R>), dim3((n2 + 255) / 256), dim3(256), 0, st,
+                     (const cx<R>*)g_f_out, (const cx<R>*)g_sh_out, (const cx<R>*)fin_a,
+                     (const cx<R>*)fin_b, pw, pl.pscale_f, pl.pscale_sh, la, lb, n2);
+  // ---- backward sweep
+  RowAdjArgs<R> ra{};
+  ra.la = la;
+  ra.lb = lb;
+  ra.tw = (const Tw<R>*)pl.tw_x;
+  ra.phase = (const cx<R>*)fws;
+  ra.ny = p.ny;
+  ra.kf = (R)pl.kappa_f;
+  ra.ks = (R)pl.kappa_sh;
+  ra.tf = (R)(pl.tpa_f / 2.0);
+  ra.ts = (R)(pl.tpa_sh / 2.0);
+  ra.h = (R)(pl.dz / 2.0);
+  ra.undepleted = (p.flags & SHG_UNDEPLETED) ? 1 : 0;
+  const size_t gstride = (size_t)L.nblk * 2;
+  auto g1 = [&](int s) { return g_dk ? gp1 + gstride * s : nullptr; };
+  auto g2 = [&](int s) { return g_dk ? gp2 + gstride * s : nullptr; };
+  auto staged = [&](int s, int b) { return stage + (size_t)(s - b) * 2 * n2; };
+  RowAdjTArgs<R> q{};
+  RowAdjTArgs<R>* qp = nullptr;
+  if (th) {
+    q.temp = (const R*)temp;
+    q.carry = carry;
+    q.moments = moments;
+    q.t_ref = (R)p.t_ref;
+    q.ddk = (R)p.ddk_dT;
+    q.lens_f = (R)pl.lens_f;
+    q.lens_sh = (R)pl.lens_sh;
+    q.dz = (R)pl.dz;
+    qp = &q;
+    hipLaunchKernelGGL((zero_carry<R>), dim3(nb), dim3(256), 0, st, carry, moments, n2);
+  }
+  auto adj = [&](RowAdjArgs<R>& a, const R* psi, int* rows) {
+    q.psi = psi;
+    return adj_dispatch<R>(p.nx, pl.row_e, pl.row_wg, &a, qp, st, rows);
+  };
+  auto spsi = [&](int s, int b) { return psi_stage + (size_t)(s - b) * n2; };
+  int rows = 1;
+  for (int k = L.segs - 1; k >= 0; --k) {
+    const int b = k * L.k, e = std::min(p.nz, b + L.k);
+    const void *ia, *ib;
+    seg_in(k, &ia, &ib);
+    FwdIO io{ia, ib, work, work + n2, work, work + n2, stage};
+    if (th) {
+      hipLaunchKernelGGL((copy_real<R>), dim3(nb), dim3(256), 0, st, (const R*)psi_ck(k),
+                         psi_work, n2);
+      io.temp = temp;
+      io.psi = psi_work;
+      io.tap_psi = psi_stage;
+    }
+    rc = enqueue_forward_io(pl, io, dk_z, b, e, fws, nullptr, st, false);
+    if (rc) return rc;
+    // top: second half-step of step e-1, lambda in real space
+    ra.ua = staged(e - 1, b);
+    ra.ub = staged(e - 1, b) + n2;
+    ra.s_second = e - 1;
+    ra.s_first = -1;
+    ra.inv_in = 0;
+    ra.fwd_out = 1;
+    ra.gp_first = nullptr;
+    ra.gp_second = g2(e - 1);
+    if (!adj(ra, spsi(e - 1, b), &rows))
+      return fail(SHG_EUNSUPPORTED, "adjoint row schedule e=%d wg=%d not built", pl.row_e,
+                  pl.row_wg);
+    for (int s = e - 1; s > b; --s) {
+      if ((rc = launch_col(pl, la, lb, 1, st))) return rc;
+      ra.ua = staged(s - 1, b);
+      ra.ub = staged(s - 1, b) + n2;
+      ra.s_second = s - 1;
+      ra.s_first = s;
+      ra.inv_in = 1;
+      ra.fwd_out = 1;
+      ra.gp_first = g1(s);
+      ra.gp_second = g2(s - 1);
+      adj(ra, spsi(s - 1, b), &rows);
+    }
+    if ((rc = launch_col(pl, la, lb, 1, st))) return rc;
+    ra.ua = (const cx<R>*)ia;
+    ra.ub = (const cx<R>*)ib;
+    ra.s_second = -1;
+    ra.s_first = b;
+    ra.inv_in = 1;
+    ra.fwd_out = 0;
+    ra.gp_first = g1(b);
+    ra.gp_second = nullptr;
+    adj(ra, th ? psi_ck(k) : nullptr, &rows);
+  }
+  if (th && g_t) {
+    hipLaunchKernelGGL(moments_finalize, dim3(1), dim3(256), 0, st, (const double*)moments, n2,
+                       g_t);
+  }
+  if (g_dk) {
+    hipLaunchKernelGGL(grad_step_sums, dim3(p.nz), dim3(256), 0, st, (const double*)gp1,
+                       (const double*)gp2, p.ny / rows, gh);
+    hipLaunchKernelGGL(grad_dk_finalize, dim3(1), dim3(256), 0, st, (const double*)gh, p.nz,
+                       pl.dz, g_dk);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return SHG_OK;
+}
+
+int propagate_adjoint(Plan& pl, const void* a_f_in, const void* a_sh_in, const double* dk_z,
+                      const void* temp, const void* g_f_out, const void* g_sh_out,
+                      const double* pw, void* g_f_in, void* g_sh_in, double* g_dk,
+                      double* g_t, void* a_f_out, void* a_sh_out, double* powers, void* ws,
+                      hipStream_t st) {
+  if (!a_f_in || !a_sh_in) return fail(SHG_EINVAL, "a_f_in and a_sh_in must be non-NULL");
+  if (!g_f_in || !g_sh_in) return fail(SHG_EINVAL, "g_f_in and g_sh_in must be non-NULL");
+  if (!ws) return fail(SHG_EINVAL, "workspace must be non-NULL (shg_workspace_bytes(plan, 1))");
+  if (g_t && !temp) return fail(SHG_EINVAL, "g_t_moments requires a temperature field");
+  int rc = sticky_device_error();
+  if (rc) return rc;
+  if (pl.dtype == SHG_C64)
+    return adjoint_t<float>(pl, a_f_in, a_sh_in, dk_z, temp, g_f_out, g_sh_out, pw, g_f_in,
+                            g_sh_in, g_dk, g_t, a_f_out, a_sh_out, powers, (char*)ws, st);
+  return adjoint_t<double>(pl, a_f_in, a_sh_in, dk_z, temp, g_f_out, g_sh_out, pw, g_f_in,
+                           g_sh_in, g_dk, g_t, a_f_out, a_sh_out, powers, (char*)ws, st);
+}
+
+}  // namespace shg
+
+using namespace shg;
+
+extern "C" int shg_propagate_adjoint(shg_plan* plan, const void* a_f_in, const void* a_sh_in,
+                                     const double* dk_z, const void* temp, const void* g_f_out,
+                                     const void* g_sh_out, const double* power_weights,
+                                     void* g_f_in, void* g_sh_in, double* g_dk_z,
+                                     double* g_t_moments, void* a_f_out, void* a_sh_out,
+                                     double* powers, void* workspace, void* stream) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  Plan* pl = reinterpret_cast<Plan*>(plan);
+  rc = propagate_adjoint(*pl, a_f_in, a_sh_in, dk_z, temp, g_f_out, g_sh_out, power_weights,
+                         g_f_in, g_sh_in, g_dk_z, g_t_moments, a_f_out, a_sh_out, powers,
+                         workspace, (hipStream_t)stream);
+  return rc ? rc : ok();
+}

@@ -70,11 +70,79 @@ __device__ __forceinline__ void rk4_cell(cx<R>& a, cx<R>& b, const HalfStep<R>& 
   b = b + scale(k1b + scale(k2b + k3b, (R)2) + k4b, h6);
 }
 
+// ---------------------------------------------------------------- temperature
+// With a temperature field the mismatch and the index are per cell.  On step s
+// the phase is phi = Phi_s + dk_s tau + ddk_dT (Psi_s + dT_s tau), tau = z - z_s,
+// where Phi_s + dk_s tau comes from the uniform table, dT_s = T_s - T_ref is the
+// mid-plane sample and Psi_s = sum_{s' < s} dT_s' dz is carried per cell.  The
+// thermal lens adds -i g_j dT_s A_j, g_j = (2 pi / lambda_j) dn/dT.
+template <typename R>
+struct HalfStepT {
+  cx<R> cf[3], cs[3];
+  R gf, gs;               // lens rates g_F dT, g_SH dT
+};
+
+__device__ __forceinline__ void sincos_r(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sincos_r(double x, double* s, double* c) { sincos(x, s, c); }
+
+// Stage coefficients at tau0, tau0 + dz/4, tau0 + dz/2 for one cell.
+template <typename R>
+__device__ __forceinline__ HalfStepT<R> thermal_coefs(const cx<R>* __restrict__ e, R kf, R ks,
+                                                      R ddk, R psi, R dT, R tau0, R qdz,
+                                                      R lens_f, R lens_sh) {
+  HalfStepT<R> h;
+  R sn, c;
+  sincos_r(ddk * (psi + dT * tau0), &sn, &c);
+  cx<R> rho = {c, -sn};
+  sincos_r(ddk * dT * qdz, &sn, &c);
+  const cx<R> step = {c, -sn};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const cx<R> ek = e[k] * rho;
+    h.cf[k] = {-kf * ek.im, kf * ek.re};
+    h.cs[k] = {ks * ek.im, ks * ek.re};
+    rho = rho * step;
+  }
+  h.gf = lens_f * dT;
+  h.gs = lens_sh * dT;
+  return h;
+}
+
+// nl_rhs plus the thermal-lens terms -i g A.
+template <typename R>
+__device__ __forceinline__ void nl_rhs_t(cx<R> a, cx<R> b, cx<R> cf, cx<R> cs, R tf, R ts, R gf,
+                                         R gs, bool und, cx<R>& fa, cx<R>& fb) {
+  nl_rhs(a, b, cf, cs, tf, ts, und, fa, fb);
+  fb = fb + cx<R>{gs * b.im, -gs * b.re};
+  if (!und) fa = fa + cx<R>{gf * a.im, -gf * a.re};
+}
+
+template <typename R>
+__device__ __forceinline__ void rk4_cell_t(cx<R>& a, cx<R>& b, const HalfStepT<R>& c, R tf, R ts,
+                                           R h, bool und) {
+  const R h2 = h * (R)0.5;
+  cx<R> k1a, k1b, k2a, k2b, k3a, k3b, k4a, k4b;
+  nl_rhs_t(a, b, c.cf[0], c.cs[0], tf, ts, c.gf, c.gs, und, k1a, k1b);
+  nl_rhs_t(a + scale(k1a, h2), b + scale(k1b, h2), c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, und, k2a,
+           k2b);
+  nl_rhs_t(a + scale(k2a, h2), b + scale(k2b, h2), c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, und, k3a,
+           k3b);
+  nl_rhs_t(a + scale(k3a, h), b + scale(k3b, h), c.cf[2], c.cs[2], tf, ts, c.gf, c.gs, und, k4a,
+           k4b);
+  const R h6 = h / (R)6;
+  a = a + scale(k1a + scale(k2a + k3a, (R)2) + k4a, h6);
+  b = b + scale(k1b + scale(k2b + k3b, (R)2) + k4b, h6);
+}
+
 // ---------------------------------------------------------------- row pass
 template <typename R>
 struct RowArgs {
-  cx<R>* a;               // fundamental [ny][nx]
-  cx<R>* b;               // second harmonic [ny][nx]
+  const cx<R>* ain;       // fundamental [ny][nx], read
+  const cx<R>* bin;       // second harmonic [ny][nx], read
+  cx<R>* aout;            // written (may equal ain: in place)
+  cx<R>* bout;
+  cx<R>* tap_a;           // optional: real-space state before the second half-step
+  cx<R>* tap_b;
   const Tw<R>* tw;        // W_nx^k, k = 0..nx-1
   const cx<R>* phase;     // [nz][5] exp(-i phi) at z_s + {0, 1/4, 1/2, 3/4, 1} dz
   double* partials;       // [gridDim.x][2] sums of |A|^2 (last pass), or null
@@ -87,6 +155,11 @@ struct RowArgs {
   R tf, ts;               // beta~_F / 2, beta~_SH / 2
   R h;                    // dz / 2
   int undepleted;
+  // temperature field (THERMAL row passes only)
+  const R* temp;          // [nz][ny][nx] mid-plane samples
+  R* psi;                 // [ny][nx] in: Psi at the oldest step touched; out: at the newest
+  R* tap_psi;             // optional: Psi_{s_second} (adjoint recompute)
+  R t_ref, ddk, lens_f, lens_sh, dz;
 };
 
 template <int G, int WG>
@@ -122,22 +195,21 @@ __device__ __forceinline__ void block_sum2(double& x, double& y, double* red) {
   }
 }
 
-template <typename R, int N, int G, int ROWS>
-__global__ void __launch_bounds__(G * ROWS) row_pass(RowArgs<R> p) {
+template <typename R, int N, int G, int ROWS, bool TH = false>
+__device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
   constexpr int E = N / G;
   constexpr int P = padded_len<N>();
   __shared__ cx<R> lds[ROWS][2][2][P];
   __shared__ double red[2 * ((G * ROWS + 63) / 64)];
   const int t = threadIdx.x % G;
   const int rr = threadIdx.x / G;
-  const int y = blockIdx.x * ROWS + rr;
-  cx<R>* __restrict__ ra = p.a + (size_t)y * N;
-  cx<R>* __restrict__ rb = p.b + (size_t)y * N;
+  const int y = blk * ROWS + rr;
+  const size_t row = (size_t)y * N;
   cx<R> va[E], vb[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
-    va[m] = ra[t + G * m];
-    vb[m] = rb[t + G * m];
+    va[m] = p.ain[row + t + G * m];
+    vb[m] = p.bin[row + t + G * m];
   }
   const LdsView<R, 1> a0{&lds[rr][0][0][0]}, a1{&lds[rr][0][1][0]};
   const LdsView<R, 1> b0{&lds[rr][1][0][0]}, b1{&lds[rr][1][1][0]};
@@ -146,15 +218,49 @@ __global__ void __launch_bounds__(G * ROWS) row_pass(RowArgs<R> p) {
     fft_regs<R, N, G, true, 1>(vb, b0, b1, t, p.tw);
   }
   const bool und = p.undepleted != 0;
-  if (p.s_second >= 0) {
-    const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);
+  if (p.tap_a) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) rk4_cell(va[m], vb[m], c, p.tf, p.ts, p.h, und);
+    for (int m = 0; m < E; ++m) {
+      p.tap_a[row + t + G * m] = va[m];
+      p.tap_b[row + t + G * m] = vb[m];
+    }
   }
-  if (p.s_first >= 0) {
-    const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks);
+  if constexpr (TH) {
+    const size_t n2 = (size_t)p.ny * N;
+    const R qdz = p.dz * (R)0.25;
 #pragma unroll
-    for (int m = 0; m < E; ++m) rk4_cell(va[m], vb[m], c, p.tf, p.ts, p.h, und);
+    for (int m = 0; m < E; ++m) {
+      const size_t idx = row + t + G * m;
+      R psi = p.psi[idx];
+      if (p.tap_psi) p.tap_psi[idx] = psi;
+      if (p.s_second >= 0) {
+        const R dT = p.temp[(size_t)p.s_second * n2 + idx] - p.t_ref;
+        const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, p.ddk, psi,
+                                             dT, p.h, qdz, p.lens_f, p.lens_sh);
+        rk4_cell_t(va[m], vb[m], c, p.tf, p.ts, p.h, und);
+        psi += dT * p.dz;
+      }
+      if (p.s_first >= 0) {
+        const R dT = p.temp[(size_t)p.s_first * n2 + idx] - p.t_ref;
+        const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, p.ddk, psi, dT,
+                                             (R)0, qdz, p.lens_f, p.lens_sh);
+        rk4_cell_t(va[m], vb[m], c, p.tf, p.ts, p.h, und);
+      }
+      // psi now holds Psi at the start of the newest step touched (s_first, or
+      // s_second + 1 after a last pass), so a march [s0, s1) leaves Psi_{s1}
+      if (p.s_second >= 0) p.psi[idx] = psi;
+    }
+  } else {
+    if (p.s_second >= 0) {
+      const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);
+#pragma unroll
+      for (int m = 0; m < E; ++m) rk4_cell(va[m], vb[m], c, p.tf, p.ts, p.h, und);
+    }
+    if (p.s_first >= 0) {
+      const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks);
+#pragma unroll
+      for (int m = 0; m < E; ++m) rk4_cell(va[m], vb[m], c, p.tf, p.ts, p.h, und);
+    }
   }
   if (p.fwd_out) {
     fft_regs<R, N, G, false, 1>(va, a0, a1, t, p.tw);
@@ -162,8 +268,8 @@ __global__ void __launch_bounds__(G * ROWS) row_pass(RowArgs<R> p) {
   }
 #pragma unroll
   for (int m = 0; m < E; ++m) {
-    ra[t + G * m] = va[m];
-    rb[t + G * m] = vb[m];
+    p.aout[row + t + G * m] = va[m];
+    p.bout[row + t + G * m] = vb[m];
   }
   if (p.partials) {
     double sa = 0.0, sb = 0.0;
@@ -174,10 +280,27 @@ __global__ void __launch_bounds__(G * ROWS) row_pass(RowArgs<R> p) {
     }
     block_sum2<G * ROWS>(sa, sb, red);
     if (threadIdx.x == 0) {
-      p.partials[2 * blockIdx.x] = sa;
-      p.partials[2 * blockIdx.x + 1] = sb;
+      p.partials[2 * blk] = sa;
+      p.partials[2 * blk + 1] = sb;
     }
   }
+}
+
+template <typename R, int N, int G, int ROWS, bool TH>
+__global__ void __launch_bounds__(G * ROWS) row_pass(RowArgs<R> p) {
+  row_body<R, N, G, ROWS, TH>(p, blockIdx.x);
+}
+
+// Psi at the start of step s_begin: sum_{s < s_begin} (T_s - T_ref) dz per cell
+// (FP64 accumulation); zero for s_begin = 0.
+template <typename R>
+__global__ void __launch_bounds__(256) psi_init(const R* __restrict__ temp, int s_begin, double t_ref,
+                                                double dz, R* __restrict__ psi, size_t n2) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n2) return;
+  double acc = 0.0;
+  for (int s = 0; s < s_begin; ++s) acc += ((double)temp[(size_t)s * n2 + i] - t_ref) * dz;
+  psi[i] = (R)acc;
 }
 
 // ---------------------------------------------------------------- column pass
@@ -189,6 +312,7 @@ struct ColArgs {
   const double* my[2];    // per wave: exp(2 i pi^2 qy^2 dz / k) exp(-alpha dz/2) / (nx ny) [ny]
   int nx;                 // row pitch in elements
   int tiles;              // column tiles per field (nx / TC)
+  int conj_prop;          // multiply by conj(M) (adjoint of the linear step)
 };
 
 // Block b -> (field, tile).  Blocks are dealt to the 8 XCDs round-robin
@@ -199,7 +323,7 @@ __device__ __forceinline__ int xcd_linear_block(int b, int nblk) {
 }
 
 template <typename R, int N, int G, int TC>
-__global__ void __launch_bounds__(G * TC) col_pass(ColArgs<R> p) {
+__device__ __forceinline__ void col_body(const ColArgs<R>& p) {
   constexpr int E = N / G;
   constexpr int P = padded_len<N>();
   __shared__ cx<R> lds[2][P * TC];
@@ -218,11 +342,12 @@ __global__ void __launch_bounds__(G * TC) col_pass(ColArgs<R> p) {
   // diffraction + linear loss (Eq. A.4), product formed in FP64
   const double* __restrict__ mxp = p.mx[field];
   const double* __restrict__ myp = p.my[field];
-  const double mxr = mxp[2 * x], mxi = mxp[2 * x + 1];
+  const double sgn = p.conj_prop ? -1.0 : 1.0;
+  const double mxr = mxp[2 * x], mxi = sgn * mxp[2 * x + 1];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int qy = t + G * m;
-    const double myr = myp[2 * qy], myi = myp[2 * qy + 1];
+    const double myr = myp[2 * qy], myi = sgn * myp[2 * qy + 1];
     const double mr = mxr * myr - mxi * myi;
     const double mi = mxr * myi + mxi * myr;
     const double vr = (double)v[m].re, vi = (double)v[m].im;
@@ -233,13 +358,18 @@ __global__ void __launch_bounds__(G * TC) col_pass(ColArgs<R> p) {
   for (int m = 0; m < E; ++m) col[(size_t)(t + G * m) * p.nx] = v[m];
 }
 
+template <typename R, int N, int G, int TC>
+__global__ void __launch_bounds__(G * TC) col_pass(ColArgs<R> p) {
+  col_body<R, N, G, TC>(p);
+}
+
 // ---------------------------------------------------------------- phase table
 // Accumulated mismatch phase (Eq. 3) for a mismatch constant within each step:
 // Phi_s = sum_{s' < s} dk_s' dz (FP64 chunked scan in one block), and
 // out[5 s + k] = exp(-i (Phi_s + dk_s k dz / 4)), k = 0..4.
 template <typename R>
-__global__ void __launch_bounds__(256) phase_table(const double* __restrict__ dk_z, double dk0,
-                                                   int nz, double dz, cx<R>* __restrict__ out) {
+__device__ __forceinline__ void phase_table_body(const double* __restrict__ dk_z, double dk0,
+                                                 int nz, double dz, cx<R>* __restrict__ out) {
   __shared__ double part[256];
   const int tid = threadIdx.x;
   const int chunk = (nz + 255) / 256;
@@ -270,9 +400,15 @@ __global__ void __launch_bounds__(256) phase_table(const double* __restrict__ dk
   }
 }
 
+template <typename R>
+__global__ void __launch_bounds__(256) phase_table(const double* __restrict__ dk_z, double dk0,
+                                                   int nz, double dz, cx<R>* __restrict__ out) {
+  phase_table_body<R>(dk_z, dk0, nz, dz, out);
+}
+
 // ---------------------------------------------------------------- powers
 // Fixed-order sum of the per-block partials; P_j = scale_j * sum |A_j|^2.
-__global__ void __launch_bounds__(256) power_finalize(const double* __restrict__ partials, int n,
+static __global__ void __launch_bounds__(256) power_finalize(const double* __restrict__ partials, int n,
                                                       double scale_f, double scale_sh,
                                                       double* __restrict__ powers) {
   __shared__ double red[8];
@@ -285,6 +421,73 @@ __global__ void __launch_bounds__(256) power_finalize(const double* __restrict__
   if (threadIdx.x == 0) {
     powers[0] = x * scale_f;
     powers[1] = y * scale_sh;
+  }
+}
+
+}  // namespace shg
+
+namespace shg {
+
+// ---------------------------------------------------------------- batches
+// One instance of a batched march.  Instances of one launch share the grid
+// size and the schedule; blockIdx.y selects the instance.  The host orders a
+// size group by decreasing nz, so the instances still marching at boundary s
+// are a prefix and a launch simply covers gridDim.y of them.
+template <typename R>
+struct BatchInst {
+  RowArgs<R> row;         // pointers and coefficients (mode fields set per launch)
+  ColArgs<R> col;
+  const double* dk_z;     // per-step mismatch or null
+  double dk0, dz;
+  double pscale_f, pscale_sh;
+  double* partials;       // [row blocks][2]
+  double* powers;         // [2] or null
+  int nz;
+  int row_blocks;
+};
+
+// Row pass at boundary s (0 <= s <= nz): second half-step of s-1 when s >= 1,
+// first half-step of s when s < nz; the last boundary leaves real space and
+// writes the power partials.
+template <typename R, int N, int G, int ROWS>
+__global__ void __launch_bounds__(G * ROWS) row_pass_batch(const BatchInst<R>* __restrict__ inst,
+                                                           int s) {
+  const BatchInst<R>& I = inst[blockIdx.y];
+  RowArgs<R> p = I.row;
+  const int nz = I.nz;
+  p.s_second = s >= 1 ? s - 1 : -1;
+  p.s_first = s < nz ? s : -1;
+  p.inv_in = s >= 1 ? 1 : 0;
+  p.fwd_out = s < nz ? 1 : 0;
+  p.partials = (s == nz && I.powers) ? I.partials : nullptr;
+  row_body<R, N, G, ROWS>(p, blockIdx.x);
+}
+
+template <typename R, int N, int G, int TC>
+__global__ void __launch_bounds__(G * TC) col_pass_batch(const BatchInst<R>* __restrict__ inst) {
+  col_body<R, N, G, TC>(inst[blockIdx.y].col);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) phase_table_batch(const BatchInst<R>* __restrict__ inst) {
+  const BatchInst<R>& I = inst[blockIdx.x];
+  phase_table_body<R>(I.dk_z, I.dk0, I.nz, I.dz, const_cast<cx<R>*>(I.row.phase));
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) power_finalize_batch(const BatchInst<R>* __restrict__ inst) {
+  __shared__ double red[8];
+  const BatchInst<R>& I = inst[blockIdx.x];
+  if (!I.powers) return;
+  double x = 0.0, y = 0.0;
+  for (int i = threadIdx.x; i < I.row_blocks; i += 256) {
+    x += I.partials[2 * i];
+    y += I.partials[2 * i + 1];
+  }
+  block_sum2<256>(x, y, red);
+  if (threadIdx.x == 0) {
+    I.powers[0] = x * I.pscale_f;
+    I.powers[1] = y * I.pscale_sh;
   }
 }
 

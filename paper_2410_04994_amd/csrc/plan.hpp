@@ -14,12 +14,14 @@ struct GraphKey {
   const void* a;
   const void* b;
   const void* dk;
+  const void* temp;
   const void* ws;
   const void* powers;
   int s0, s1;
   int re, rw, ce, ct;
   bool operator==(const GraphKey& o) const {
-    return a == o.a && b == o.b && dk == o.dk && ws == o.ws && powers == o.powers && s0 == o.s0 &&
+    return a == o.a && b == o.b && dk == o.dk && temp == o.temp && ws == o.ws &&
+           powers == o.powers && s0 == o.s0 &&
            s1 == o.s1 && re == o.re && rw == o.rw && ce == o.ce && ct == o.ct;
   }
 };
@@ -61,6 +63,30 @@ struct Plan {
   size_t ev_used = 0;
   // adjoint state (owned by adjoint.hip)
   void* adj = nullptr;
+  // batch cache (owned by batch.hip) when this plan is the first of a batch
+  void* batch = nullptr;
+};
+
+// Pointers of one forward march: the first row pass reads (a_in, b_in), the
+// passes work in place on (a_work, b_work), the last row pass writes
+// (a_out, b_out).  tap (optional) receives, for every step s of the range, the
+// real-space state before its second half-step at tap + (s - s0) * 2 * nx * ny
+// (F then SH).
+// temp (optional) is the [nz][ny][nx] temperature field; psi (optional) is
+// the per-cell accumulated (T - T_ref) dz buffer holding Psi at s0 (when NULL
+// the workspace buffer is used and initialised from temp); tap_psi receives
+// Psi at the start of each step s at tap_psi + (s - s0) * nx * ny.
+struct FwdIO {
+  const void* a_in;
+  const void* b_in;
+  void* a_work;
+  void* b_work;
+  void* a_out;
+  void* b_out;
+  void* tap;
+  const void* temp = nullptr;
+  void* psi = nullptr;
+  void* tap_psi = nullptr;
 };
 
 // shg.hip
@@ -72,14 +98,18 @@ int sticky_device_error();
 size_t forward_ws_bytes(const Plan& pl);
 int enqueue_forward(Plan& pl, void* a, void* b, const double* dk_z, int s0, int s1, void* ws,
                     double* powers, hipStream_t st);
+int enqueue_forward_io(Plan& pl, const FwdIO& io, const double* dk_z, int s0, int s1, void* ws,
+                       double* powers, hipStream_t st, bool make_phase);
 int ensure_own_ws(Plan& pl, size_t bytes);
+size_t align256(size_t v);
+int launch_col(Plan& pl, void* a, void* b, int conj, hipStream_t st);
 bool row_supported(const Plan& pl, int e, int wg, int* rows);
 bool col_supported(const Plan& pl, int e, int tc);
 
 // adjoint.hip / thermal.hip / batch.hip
 size_t adjoint_ws_bytes(const Plan& pl);
 void free_adjoint(Plan& pl);
-int propagate_temp(Plan& pl, void* a_f, void* a_sh, const double* dk_z, const void* temp, int s0,
-                   int s1, void* ws, double* powers, hipStream_t st);
+void free_batch(Plan& pl);
+
 
 }  // namespace shg

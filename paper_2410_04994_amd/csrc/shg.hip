@@ -107,7 +107,12 @@ bool row_try(int e, int wg, const RowArgs<R>* a, hipStream_t st, int* rows_out, 
     using S = RowShape<G, WG>;
     if (rows_out) *rows_out = S::rows;
     if (a) {
-      launch(row_pass<R, N, G, S::rows>, dim3(a->ny / S::rows), dim3(S::threads), st, tm, 0, *a);
+      if (a->temp)
+        launch(row_pass<R, N, G, S::rows, true>, dim3(a->ny / S::rows), dim3(S::threads), st, tm,
+               0, *a);
+      else
+        launch(row_pass<R, N, G, S::rows, false>, dim3(a->ny / S::rows), dim3(S::threads), st, tm,
+               0, *a);
     }
     return true;
   } else {
@@ -368,28 +373,36 @@ void free_plan_tables(Plan& pl) {
   pl.own_ws = nullptr;
   pl.batch_ws = nullptr;
   free_adjoint(pl);
+  free_batch(pl);
 }
 
 // ---------------------------------------------------------------- forward
-static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 size_t forward_ws_bytes(const Plan& pl) {
   const size_t phase = (size_t)pl.p.nz * 5 * 2 * pl.real_bytes;
   const size_t parts = (size_t)pl.p.ny * 2 * sizeof(double);
-  return align256(phase) + align256(parts);
+  const size_t psi = (size_t)pl.p.nx * pl.p.ny * pl.real_bytes;
+  return align256(phase) + align256(parts) + align256(psi);
 }
 
 template <typename R>
-static int enqueue_forward_t(Plan& pl, cx<R>* a, cx<R>* b, const double* dk_z, int s0, int s1,
-                             char* ws, double* powers, hipStream_t st) {
+static int enqueue_forward_t(Plan& pl, const FwdIO& io, const double* dk_z, int s0, int s1,
+                             char* ws, double* powers, hipStream_t st, bool make_phase) {
   const shg_params& p = pl.p;
   cx<R>* phase = (cx<R>*)ws;
   double* partials = (double*)(ws + align256((size_t)p.nz * 5 * sizeof(cx<R>)));
-  hipLaunchKernelGGL((phase_table<R>), dim3(1), dim3(256), 0, st, dk_z, p.dk0, p.nz, pl.dz,
-                     phase);
+  R* psi = (R*)(ws + align256((size_t)p.nz * 5 * sizeof(cx<R>)) +
+                align256((size_t)p.ny * 2 * sizeof(double)));
+  if (make_phase) {
+    hipLaunchKernelGGL((phase_table<R>), dim3(1), dim3(256), 0, st, dk_z, p.dk0, p.nz, pl.dz,
+                       phase);
+  }
+  const size_t n2 = (size_t)p.nx * p.ny;
+  cx<R>* wa = (cx<R>*)io.a_work;
+  cx<R>* wb = (cx<R>*)io.b_work;
+  cx<R>* tap = (cx<R>*)io.tap;
   RowArgs<R> ra{};
-  ra.a = a;
-  ra.b = b;
   ra.tw = (const Tw<R>*)pl.tw_x;
   ra.phase = phase;
   ra.ny = p.ny;
@@ -399,9 +412,23 @@ static int enqueue_forward_t(Plan& pl, cx<R>* a, cx<R>* b, const double* dk_z, i
   ra.ts = (R)(pl.tpa_sh / 2.0);
   ra.h = (R)(pl.dz / 2.0);
   ra.undepleted = (p.flags & SHG_UNDEPLETED) ? 1 : 0;
+  if (io.temp) {
+    ra.temp = (const R*)io.temp;
+    ra.psi = io.psi ? (R*)io.psi : psi;
+    ra.t_ref = (R)p.t_ref;
+    ra.ddk = (R)p.ddk_dT;
+    ra.lens_f = (R)pl.lens_f;
+    ra.lens_sh = (R)pl.lens_sh;
+    ra.dz = (R)pl.dz;
+    if (!io.psi) {
+      hipLaunchKernelGGL((psi_init<R>), dim3((n2 + 255) / 256), dim3(256), 0, st, ra.temp, s0,
+                         p.t_ref, pl.dz, ra.psi, n2);
+    }
+  }
+  R* tap_psi = (R*)io.tap_psi;
   ColArgs<R> ca{};
-  ca.f[0] = a;
-  ca.f[1] = b;
+  ca.f[0] = wa;
+  ca.f[1] = wb;
   ca.tw = (const Tw<R>*)pl.tw_y;
   for (int w = 0; w < 2; ++w) {
     ca.mx[w] = pl.mx[w];
@@ -409,9 +436,15 @@ static int enqueue_forward_t(Plan& pl, cx<R>* a, cx<R>* b, const double* dk_z, i
   }
   ca.nx = p.nx;
   ca.tiles = p.nx / pl.col_tc;
+  ca.conj_prop = 0;
   int rows = 1;
   LaunchTimer tm{&pl};
   // first row pass: N(dz/2) of step s0, then FFT_x
+  ra.ain = (const cx<R>*)io.a_in;
+  ra.bin = (const cx<R>*)io.b_in;
+  ra.aout = wa;
+  ra.bout = wb;
+  ra.tap_a = ra.tap_b = nullptr;
   ra.s_second = -1;
   ra.s_first = s0;
   ra.inv_in = 0;
@@ -423,6 +456,13 @@ static int enqueue_forward_t(Plan& pl, cx<R>* a, cx<R>* b, const double* dk_z, i
     if (!col_dispatch<R>(p.ny, pl.col_e, pl.col_tc, &ca, st, &tm))
       return fail(SHG_EUNSUPPORTED, "column schedule e=%d tc=%d not built", pl.col_e, pl.col_tc);
     const bool last = (s == s1 - 1);
+    ra.ain = wa;
+    ra.bin = wb;
+    ra.aout = last ? (cx<R>*)io.a_out : wa;
+    ra.bout = last ? (cx<R>*)io.b_out : wb;
+    ra.tap_a = tap ? tap + (size_t)(s - s0) * 2 * n2 : nullptr;
+    ra.tap_b = tap ? tap + (size_t)(s - s0) * 2 * n2 + n2 : nullptr;
+    ra.tap_psi = tap_psi ? tap_psi + (size_t)(s - s0) * n2 : nullptr;
     ra.s_second = s;
     ra.s_first = last ? -1 : s + 1;
     ra.inv_in = 1;
@@ -439,13 +479,57 @@ static int enqueue_forward_t(Plan& pl, cx<R>* a, cx<R>* b, const double* dk_z, i
   return SHG_OK;
 }
 
+int enqueue_forward_io(Plan& pl, const FwdIO& io, const double* dk_z, int s0, int s1, void* ws,
+                       double* powers, hipStream_t st, bool make_phase) {
+  if (pl.dtype == SHG_C64)
+    return enqueue_forward_t<float>(pl, io, dk_z, s0, s1, (char*)ws, powers, st, make_phase);
+  return enqueue_forward_t<double>(pl, io, dk_z, s0, s1, (char*)ws, powers, st, make_phase);
+}
+
+int launch_col(Plan& pl, void* a, void* b, int conj, hipStream_t st) {
+  bool okk;
+  if (pl.dtype == SHG_C64) {
+    ColArgs<float> ca{};
+    ca.f[0] = (cx<float>*)a;
+    ca.f[1] = (cx<float>*)b;
+    ca.tw = (const Tw<float>*)pl.tw_y;
+    for (int w = 0; w < 2; ++w) {
+      ca.mx[w] = pl.mx[w];
+      ca.my[w] = pl.my[w];
+    }
+    ca.nx = pl.p.nx;
+    ca.tiles = pl.p.nx / pl.col_tc;
+    ca.conj_prop = conj;
+    okk = col_dispatch<float>(pl.p.ny, pl.col_e, pl.col_tc, &ca, st);
+  } else {
+    ColArgs<double> ca{};
+    ca.f[0] = (cx<double>*)a;
+    ca.f[1] = (cx<double>*)b;
+    ca.tw = (const Tw<double>*)pl.tw_y;
+    for (int w = 0; w < 2; ++w) {
+      ca.mx[w] = pl.mx[w];
+      ca.my[w] = pl.my[w];
+    }
+    ca.nx = pl.p.nx;
+    ca.tiles = pl.p.nx / pl.col_tc;
+    ca.conj_prop = conj;
+    okk = col_dispatch<double>(pl.p.ny, pl.col_e, pl.col_tc, &ca, st);
+  }
+  if (!okk) return fail(SHG_EUNSUPPORTED, "column schedule e=%d tc=%d not built", pl.col_e, pl.col_tc);
+  return SHG_OK;
+}
+
 int enqueue_forward(Plan& pl, void* a, void* b, const double* dk_z, int s0, int s1, void* ws,
                     double* powers, hipStream_t st) {
-  if (pl.dtype == SHG_C64)
-    return enqueue_forward_t<float>(pl, (cx<float>*)a, (cx<float>*)b, dk_z, s0, s1, (char*)ws,
-                                    powers, st);
-  return enqueue_forward_t<double>(pl, (cx<double>*)a, (cx<double>*)b, dk_z, s0, s1, (char*)ws,
-                                   powers, st);
+  FwdIO io{a, b, a, b, a, b, nullptr};
+  return enqueue_forward_io(pl, io, dk_z, s0, s1, ws, powers, st, true);
+}
+
+int enqueue_forward_temp(Plan& pl, void* a, void* b, const double* dk_z, const void* temp, int s0,
+                         int s1, void* ws, double* powers, hipStream_t st) {
+  FwdIO io{a, b, a, b, a, b, nullptr};
+  io.temp = temp;
+  return enqueue_forward_io(pl, io, dk_z, s0, s1, ws, powers, st, true);
 }
 
 int ensure_own_ws(Plan& pl, size_t bytes) {
@@ -467,15 +551,15 @@ int ensure_own_ws(Plan& pl, size_t bytes) {
 
 // Replays a cached graph of the whole launch sequence when the arguments are
 // the same as last time; otherwise captures a new one on a private stream.
-static int run_forward(Plan& pl, void* a, void* b, const double* dk_z, int s0, int s1, void* ws,
-                       double* powers, hipStream_t st) {
+static int run_forward(Plan& pl, void* a, void* b, const double* dk_z, const void* temp, int s0,
+                       int s1, void* ws, double* powers, hipStream_t st) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   hipError_t e = hipStreamIsCapturing(st, &cs);
   if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
   const bool use_graph = !(pl.p.flags & SHG_NO_GRAPH) && !pl.timing &&
                          cs == hipStreamCaptureStatusNone && (s1 - s0) >= 2;
-  if (!use_graph) return enqueue_forward(pl, a, b, dk_z, s0, s1, ws, powers, st);
-  GraphKey key{a, b, dk_z, ws, powers, s0, s1, pl.row_e, pl.row_wg, pl.col_e, pl.col_tc};
+  if (!use_graph) return enqueue_forward_temp(pl, a, b, dk_z, temp, s0, s1, ws, powers, st);
+  GraphKey key{a, b, dk_z, temp, ws, powers, s0, s1, pl.row_e, pl.row_wg, pl.col_e, pl.col_tc};
   if (!pl.gexec || !(key == pl.gkey)) {
     if (pl.gexec) {
       (void)hipGraphExecDestroy(pl.gexec);
@@ -487,7 +571,7 @@ static int run_forward(Plan& pl, void* a, void* b, const double* dk_z, int s0, i
     }
     e = hipStreamBeginCapture(pl.cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    int rc = enqueue_forward(pl, a, b, dk_z, s0, s1, ws, powers, pl.cap_stream);
+    int rc = enqueue_forward_temp(pl, a, b, dk_z, temp, s0, s1, ws, powers, pl.cap_stream);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(pl.cap_stream, &g);
     if (rc != SHG_OK) {
@@ -526,14 +610,13 @@ int propagate(Plan& pl, void* a_f, void* a_sh, const double* dk_z, const void* t
   if (!a_f || !a_sh) return fail(SHG_EINVAL, "a_f and a_sh must be non-NULL device pointers");
   if (!(0 <= s0 && s0 < s1 && s1 <= pl.p.nz))
     return fail(SHG_EINVAL, "step range [%d, %d) not within [0, nz=%d]", s0, s1, pl.p.nz);
-  if (temp) return propagate_temp(pl, a_f, a_sh, dk_z, temp, s0, s1, ws, powers, st);
   int rc = sticky_device_error();
   if (rc) return rc;
   if (!ws) {
     if ((rc = ensure_own_ws(pl, forward_ws_bytes(pl)))) return rc;
     ws = pl.own_ws;
   }
-  return run_forward(pl, a_f, a_sh, dk_z, s0, s1, ws, powers, st);
+  return run_forward(pl, a_f, a_sh, dk_z, temp, s0, s1, ws, powers, st);
 }
 
 }  // namespace shg

@@ -1,0 +1,215 @@
+"""Hand-written adjoint of the HIP march against the oracle's reverse-mode
+derivative and against finite differences (needs the GPU)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import adjoint as oadj
+from gpu_util import inputs, rel
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def cuda(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def gpu_adjoint(wl, dtype, a0, b0, gf, gs, w, dk=None, ckpt=0):
+    from paper_2410_04994_amd import Plan
+    plan = Plan(wl.params(), dtype, checkpoint_every=ckpt)
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    res = plan.adjoint(cuda(a0.astype(npdt)), cuda(b0.astype(npdt)),
+                       g_f_out=cuda(gf.astype(npdt)) if gf is not None else None,
+                       g_sh_out=cuda(gs.astype(npdt)) if gs is not None else None,
+                       power_weights=cuda(np.asarray(w, np.float64)),
+                       dk_z=cuda(dk) if dk is not None else None, want_dk=True)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in res.items()}
+
+
+def small_case(n=32, nz=20, seed=3, undepleted=False):
+    wl = workloads.c2_plain_c64().with_(nx=n, ny=n, nz=nz, lcr=4e-3, undepleted=undepleted,
+                                        lx=workloads.c2_plain_c64().lx * n / 256 * 2,
+                                        ly=workloads.c2_plain_c64().ly * n / 256 * 2)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a0, b0 = inputs(wl, "c128")
+    b0 = (0.05 * np.abs(a0).max() * (rng.normal(size=a0.shape) + 1j * rng.normal(size=a0.shape)))
+    gf = rng.normal(size=a0.shape) + 1j * rng.normal(size=a0.shape)
+    gs = rng.normal(size=a0.shape) + 1j * rng.normal(size=a0.shape)
+    scale = 1.0 / np.abs(a0).max()
+    dk = wl.dk0 + 500.0 * rng.normal(size=nz)
+    return wl, a0, b0, gf * scale, gs * scale, (0.3, 2.0), dk
+
+
+def oracle_adjoint(wl, a0, b0, gf, gs, w, dk):
+    return oadj.adjoint(wl.params(), a0, b0, gf, gs, dk_z=dk, power_weights=w)
+
+
+@pytest.mark.parametrize("undepleted", [False, True])
+def test_complex128_adjoint_matches_oracle(undepleted):
+    wl, a0, b0, gf, gs, w, dk = small_case(undepleted=undepleted)
+    ref = oracle_adjoint(wl, a0, b0, gf, gs, w, dk)
+    got = gpu_adjoint(wl, "c128", a0, b0, gf, gs, w, dk, ckpt=6)
+    assert rel(got["g_f"], ref["g_f"]) < 1e-10
+    assert rel(got["g_sh"], ref["g_sh"]) < 1e-10
+    assert rel(got["g_dk"], ref["g_dk"]) < 1e-10
+    assert rel(got["a_sh"], ref["forward"]["a_sh"]) < 1e-12
+
+
+def test_complex64_adjoint_matches_oracle():
+    wl, a0, b0, gf, gs, w, dk = small_case(n=64, nz=40)
+    ref = oracle_adjoint(wl, a0, b0, gf, gs, w, dk)
+    got = gpu_adjoint(wl, "c64", a0.astype(np.complex64).astype(complex),
+                      b0.astype(np.complex64).astype(complex), gf, gs, w, dk, ckpt=7)
+    assert rel(got["g_f"], ref["g_f"]) < 1e-4
+    assert rel(got["g_sh"], ref["g_sh"]) < 1e-4
+    assert rel(got["g_dk"], ref["g_dk"]) < 1e-4
+
+
+def test_checkpoint_interval_does_not_change_the_result():
+    """The recompute replays the same passes, so fields, powers and input
+    gradients are bitwise independent of K.  The mismatch gradient sums stage
+    values recomputed inside the adjoint kernel, whose code generation (FMA
+    contraction) may differ from the forward kernel's by an ulp per cell, so it
+    is compared to 1e-6."""
+    wl, a0, b0, gf, gs, w, dk = small_case(n=32, nz=13)
+    base = gpu_adjoint(wl, "c64", a0, b0, gf, gs, w, dk, ckpt=1)
+    for k in (2, 5, 13, 64):
+        got = gpu_adjoint(wl, "c64", a0, b0, gf, gs, w, dk, ckpt=k)
+        for key in ("g_f", "g_sh", "a_f", "a_sh", "powers"):
+            assert np.array_equal(got[key], base[key]), (k, key)
+        assert rel(got["g_dk"], base["g_dk"]) < 1e-6
+
+
+def test_full_grid_power_gradient_matches_oracle():
+    """256 x 256 differentiation workload (20 mm, 10 W, xi = 2.84, phase mask
+    0.1 rad), shortened to 100 steps so the FP64 oracle adjoint stays quick."""
+    wl = workloads.c4_diff_c64().with_(nz=100)
+    a0, b0 = inputs(wl, "c64")
+    a0 = a0.astype(complex)
+    b0 = b0.astype(complex)
+    dk = np.full(wl.nz, wl.dk0)
+    zero = np.zeros_like(a0)
+    ref = oracle_adjoint(wl, a0, b0, zero, zero, (0.0, 1.0), dk)
+    got = gpu_adjoint(wl, "c64", a0, b0, None, None, (0.0, 1.0), dk, ckpt=32)
+    assert rel(got["g_f"], ref["g_f"]) < 1e-4
+    assert rel(got["g_dk"], ref["g_dk"]) < 1e-4
+
+
+def test_autograd_power_gradient_finite_differences():
+    """d P_SH / d(theta, dk_z, focus) through torch: phase mask -> beam builder ->
+    march; checked by central differences of the complex128 march."""
+    from paper_2410_04994_amd import Plan, beams
+    from paper_2410_04994_amd.autograd import march
+    wl = workloads.c4_diff_c64().with_(nx=64, ny=64, nz=60,
+                                       lx=workloads.c4_diff_c64().lx * 0.5,
+                                       ly=workloads.c4_diff_c64().ly * 0.5)
+    plan = Plan(wl.params(), "c128")
+    theta0 = torch.from_numpy(workloads.phase_noise(wl)).cuda()
+    dk0 = torch.full((wl.nz,), wl.dk0, dtype=torch.float64, device="cuda")
+    focus0 = torch.tensor(wl.focus, dtype=torch.float64, device="cuda")
+
+    def psh(theta, dk, focus):
+        a = beams.pump_for(wl, theta=theta, dtype=torch.complex128, focus=focus)
+        _, _, pw = march(plan, a, torch.zeros_like(a), dk_z=dk)
+        return pw[1]
+
+    th = theta0.clone().requires_grad_(True)
+    dk = dk0.clone().requires_grad_(True)
+    fo = focus0.clone().requires_grad_(True)
+    p = psh(th, dk, fo)
+    p.backward()
+    rng = np.random.Generator(np.random.PCG64(40))
+    dz = wl.lcr / wl.nz
+    for _ in range(4):
+        v = torch.from_numpy(rng.normal(size=theta0.shape)).cuda()
+        vk = torch.from_numpy(rng.normal(size=wl.nz)).cuda() / (dz * math.sqrt(wl.nz))
+        h = 1e-3
+        with torch.no_grad():
+            fd = (psh(theta0 + h * v, dk0 + h * vk, focus0) - psh(theta0 - h * v, dk0 - h * vk, focus0)) / (2 * h)
+        an = (th.grad * v).sum() + (dk.grad * vk).sum()
+        assert abs(fd.item() - an.item()) <= 1e-5 * abs(fd.item()), (fd.item(), an.item())
+    hf = 1e-6
+    with torch.no_grad():
+        fd = (psh(theta0, dk0, focus0 + hf) - psh(theta0, dk0, focus0 - hf)) / (2 * hf)
+    assert abs(fd.item() - fo.grad.item()) <= 1e-4 * abs(fd.item())
+
+
+def test_adjoint_rejects_missing_workspace_and_outputs():
+    from paper_2410_04994_amd import Plan, ShgError
+    from paper_2410_04994_amd import binding
+    wl = workloads.c2_plain_c64().with_(nx=32, ny=32, nz=4)
+    plan = Plan(wl.params(), "c64")
+    a = torch.zeros((32, 32), dtype=torch.complex64, device="cuda")
+    lib = binding.load_library()
+    rc = lib.shg_propagate_adjoint(plan.handle, a.data_ptr(), a.data_ptr(), None, None, None, None,
+                                   None, a.data_ptr(), a.data_ptr(), None, None, None, None, None,
+                                   None, None)
+    assert rc == binding.SHG_EINVAL and b"workspace" in lib.shg_last_error()
+
+
+def thermal_small(n=32, nz=18, undepleted=False):
+    base = workloads.c5_thermal_c64()
+    wl = base.with_(nx=n, ny=n, nz=nz, lcr=6e-3, lx=base.lx * n / 512 * 4, ly=base.ly * n / 512 * 4,
+                    undepleted=undepleted)
+    temp = workloads.radial_temperature_profile(wl)
+    rng = np.random.Generator(np.random.PCG64(8))
+    temp = temp + 0.5 * rng.normal(size=temp.shape)
+    return wl, temp
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-4)])
+def test_thermal_adjoint_matches_oracle(dtype, tol):
+    from paper_2410_04994_amd import Plan
+    wl, temp = thermal_small()
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    rdt = np.float32 if dtype == "c64" else np.float64
+    temp = temp.astype(rdt)
+    a0, b0 = inputs(wl, dtype)
+    rng = np.random.Generator(np.random.PCG64(5))
+    dk = wl.dk0 + 300 * rng.normal(size=wl.nz)
+    w = (0.2, 1.0)
+    ref = oadj.adjoint(wl.params(), a0.astype(complex), b0.astype(complex), np.zeros(a0.shape, complex),
+                       np.zeros(a0.shape, complex), dk_z=dk, temp=temp.astype(np.float64),
+                       power_weights=w)
+    plan = Plan(wl.params(), dtype, checkpoint_every=5)
+    res = plan.adjoint(cuda(a0), cuda(b0), power_weights=cuda(np.asarray(w)), dk_z=cuda(dk),
+                       temp=cuda(temp), want_dk=True, want_t=True)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in res.items()}
+    assert rel(got["g_f"], ref["g_f"]) < tol
+    assert rel(got["g_dk"], ref["g_dk"]) < tol
+    assert rel(got["g_t_moments"], ref["g_t_moments"]) < tol
+
+
+def test_thermal_scalar_gradients_by_finite_differences():
+    """dP_SH/d(dT scale) and dP_SH/dT0 of the thermal-lens workload shape,
+    through torch, against central differences of the complex128 march."""
+    from paper_2410_04994_amd import Plan, beams
+    from paper_2410_04994_amd.autograd import thermal_powers
+    base = workloads.c5_thermal_c64()
+    wl = base.with_(nx=64, ny=64, nz=40, lx=base.lx * 0.5, ly=base.ly * 0.5)
+    plan = Plan(wl.params(), "c128")
+    prof = workloads.radial_temperature_profile(wl) - wl.extra["t0"]
+    prof = torch.from_numpy(prof).cuda()
+    a = beams.pump_for(wl, dtype=torch.complex128)
+    b = torch.zeros_like(a)
+    t0 = torch.tensor(wl.extra["t0"], dtype=torch.float64, device="cuda", requires_grad=True)
+    sc = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    thermal_powers(plan, a, b, t0, sc, prof)[1].backward()
+    with torch.no_grad():
+        f = lambda tt, ss: thermal_powers(plan, a, b, tt, ss, prof)[1].item()
+        h = 1e-3
+        fd_t0 = (f(t0 + h, sc) - f(t0 - h, sc)) / (2 * h)
+        fd_sc = (f(t0, sc + h) - f(t0, sc - h)) / (2 * h)
+    assert abs(t0.grad.item() - fd_t0) <= 1e-5 * abs(fd_t0) + 1e-12
+    assert abs(sc.grad.item() - fd_sc) <= 1e-5 * abs(fd_sc) + 1e-12

@@ -1,0 +1,124 @@
+"""Batched march: every instance equals its own single-instance march, sampled
+instances match the oracle, graph replays are deterministic (needs the GPU)."""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import inputs, run_oracle, compare, rel
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def small_batch(n=24, seed=9, max_nz=30):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    base = workloads.c3_batch(n_instances=n, seed=seed)
+    for i, w in enumerate(base):
+        size = [32, 64, 128][i % 3]
+        out.append(w.with_(nx=size, ny=size, nz=int(rng.integers(3, max_nz + 1)),
+                           lx=w.lx * size / w.nx, ly=w.ly * size / w.nx))
+    return out
+
+
+def run_batch(wls, dtype="c64", dk=None):
+    from paper_2410_04994_amd import Plan, propagate_batch
+    plans = [Plan(w.params(), dtype) for w in wls]
+    ins = [inputs(w, dtype) for w in wls]
+    a = [torch.from_numpy(x[0]).cuda() for x in ins]
+    b = [torch.from_numpy(x[1]).cuda() for x in ins]
+    dks = [torch.from_numpy(d).cuda() for d in dk] if dk is not None else None
+    pw = propagate_batch(plans, a, b, dk_z=dks)
+    torch.cuda.synchronize()
+    return plans, ins, [x.cpu().numpy() for x in a], [x.cpu().numpy() for x in b], pw.cpu().numpy()
+
+
+def test_batch_equals_single_instance_runs_bitwise():
+    from paper_2410_04994_amd import Plan
+    wls = small_batch()
+    plans, ins, A, B, pw = run_batch(wls)
+    for i, w in enumerate(wls):
+        p = Plan(w.params(), "c64")
+        a = torch.from_numpy(ins[i][0]).cuda()
+        b = torch.from_numpy(ins[i][1]).cuda()
+        pp = p.propagate(a, b)
+        torch.cuda.synchronize()
+        assert np.array_equal(a.cpu().numpy(), A[i]), i
+        assert np.array_equal(b.cpu().numpy(), B[i]), i
+        assert np.array_equal(pp.cpu().numpy(), pw[i]), i
+
+
+def test_batch_matches_oracle_and_replays_deterministically():
+    from paper_2410_04994_amd import Plan, propagate_batch
+    wls = small_batch(n=9, seed=4, max_nz=20)
+    rng = np.random.Generator(np.random.PCG64(2))
+    dk = [w.dk0 + 200 * rng.normal(size=w.nz) for w in wls]
+    plans = [Plan(w.params(), "c64") for w in wls]
+    ins = [inputs(w) for w in wls]
+    dks = [torch.from_numpy(d).cuda() for d in dk]
+    results = []
+    for rep in range(3):      # first call runs directly, later calls replay the graph
+        a = [torch.from_numpy(x[0]).cuda() for x in ins]
+        b = [torch.from_numpy(x[1]).cuda() for x in ins]
+        if rep == 0:
+            keep = (a, b)
+        else:
+            for x, y in zip(keep[0], a):
+                x.copy_(y)
+            for x, y in zip(keep[1], b):
+                x.copy_(y)
+            a, b = keep
+        pw = propagate_batch(plans, a, b, dk_z=dks)
+        torch.cuda.synchronize()
+        results.append(([x.cpu().numpy() for x in a], [x.cpu().numpy() for x in b], pw.cpu().numpy()))
+    for r in results[1:]:
+        assert all(np.array_equal(x, y) for x, y in zip(r[0], results[0][0]))
+        assert all(np.array_equal(x, y) for x, y in zip(r[1], results[0][1]))
+        assert np.array_equal(r[2], results[0][2])
+    A, B, pw = results[0]
+    for i, w in enumerate(wls):
+        ref = run_oracle(w, ins[i][0], ins[i][1], dk_z=dk[i])
+        compare(w, (A[i], B[i], pw[i]), ref, "c64", f"batch[{i}] {w.nx}x{w.ny}x{w.nz}")
+
+
+def test_mixed_size_sweep_sampled_against_oracle():
+    """The 512-instance sweep (64/128/256 in 1:2:1, nz in [200, 1000]) with its
+    steps cut by 8 so the oracle check stays quick; every instance is checked
+    against its own single-instance march, the smallest of each size against
+    the oracle."""
+    from paper_2410_04994_amd import Plan
+    wls = [w.with_(nz=max(1, w.nz // 8)) for w in workloads.c3_batch()]
+    plans, ins, A, B, pw = run_batch(wls)
+    rng = np.random.Generator(np.random.PCG64(77))
+    for i in rng.choice(len(wls), size=24, replace=False):
+        w = wls[i]
+        p = Plan(w.params(), "c64")
+        a = torch.from_numpy(ins[i][0]).cuda()
+        b = torch.from_numpy(ins[i][1]).cuda()
+        p.propagate(a, b)
+        torch.cuda.synchronize()
+        assert np.array_equal(b.cpu().numpy(), B[i]), i
+    for size in (64, 128, 256):
+        idx = min((i for i, w in enumerate(wls) if w.nx == size), key=lambda i: wls[i].nz)
+        w = wls[idx]
+        ref = run_oracle(w, ins[idx][0], ins[idx][1])
+        compare(w, (A[idx], B[idx], pw[idx]), ref, "c64", f"sweep[{idx}] {size}x{size}x{w.nz}")
+
+
+def test_batch_argument_errors():
+    from paper_2410_04994_amd import Plan, ShgError, propagate_batch
+    w = small_batch(n=2)
+    p64 = Plan(w[0].params(), "c64")
+    p128 = Plan(w[1].params(), "c128")
+    a = torch.zeros((w[0].ny, w[0].nx), dtype=torch.complex64, device="cuda")
+    b = torch.zeros((w[1].ny, w[1].nx), dtype=torch.complex128, device="cuda")
+    with pytest.raises(ShgError, match="dtype"):
+        propagate_batch([p64, p128], [a, b], [a, b])
+    with pytest.raises(ShgError, match="SHG_EINVAL"):
+        propagate_batch([], [], [])

@@ -165,3 +165,50 @@ def test_gpu_beam_builder_matches_oracle_builder():
     assert rel(g, o) < 1e-12
     c = ssfm.coefficients(wl.params())
     assert abs(ssfm.power(g, wl.n_f, c.dx, c.dy) / wl.power - 1) < 1e-6
+
+
+def thermal_case(n=64, nz=60):
+    base = workloads.c5_thermal_c64()
+    wl = base.with_(nx=n, ny=n, nz=nz, lx=base.lx * n / 512 * 4, ly=base.ly * n / 512 * 4)
+    temp = workloads.radial_temperature_profile(wl).astype(np.float32)
+    return wl, temp
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_temperature_field_forward(dtype):
+    """Synthetic thermal-lens field T0 + 3 K exp(-alpha_SH z) exp(-2 r^2 / w_T^2):
+    per-cell mismatch and lens phases."""
+    wl, temp = thermal_case()
+    plan = make_plan(wl, dtype)
+    a0, b0 = inputs(wl, dtype)
+    gpu = run_gpu(plan, a0, b0, temp=temp)
+    ref = run_oracle(wl, a0, b0, temp=temp.astype(np.float64))
+    compare(wl, gpu, ref, dtype, "thermal " + plan.describe())
+    # the field matters: without it the result differs well beyond the tolerance
+    cold = run_oracle(wl, a0, b0)
+    assert rel(ref["a_sh"], cold["a_sh"]) > 1e-2
+
+
+def test_temperature_field_resume_and_profile():
+    wl, temp = thermal_case(n=32, nz=24)
+    rng = np.random.Generator(np.random.PCG64(3))
+    dk = wl.dk0 + 100 * rng.normal(size=wl.nz)
+    plan = make_plan(wl)
+    a0, b0 = inputs(wl)
+    part = run_gpu(plan, a0, b0, dk_z=dk, temp=temp, s_end=10)
+    rest = run_gpu(plan, part[0], part[1], dk_z=dk, temp=temp, s_begin=10)
+    ref = run_oracle(wl, a0, b0, dk_z=dk, temp=temp.astype(np.float64))
+    compare(wl, rest, ref, "c64", "thermal resume")
+
+
+def test_temperature_field_full_grid():
+    """512 x 512 thermal-lens workload (50 W, xi = 2.84), shortened to 40 steps
+    for the oracle, with the default schedule."""
+    base = workloads.c5_thermal_c64()
+    wl = base.with_(nz=40)
+    temp = workloads.radial_temperature_profile(base)[:40].astype(np.float32)
+    plan = make_plan(wl)
+    a0, b0 = inputs(wl)
+    gpu = run_gpu(plan, a0, b0, temp=temp)
+    ref = run_oracle(wl, a0, b0, temp=temp.astype(np.float64))
+    compare(wl, gpu, ref, "c64", "thermal 512 " + plan.describe())
