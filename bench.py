@@ -98,9 +98,11 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    from paper_2410_04994_amd import autotune
     dev = torch.device("cuda:0")
     wl = workloads.c2_plain_c64()
     plan = Plan(wl.params(), "c64")
+    autotune.tune_single(plan)
     theta = torch.from_numpy(workloads.phase_noise(wl)).to(dev)
     a_in = beams.pump_for(wl, theta=theta, dtype=torch.complex64, device=dev)
     b_in = torch.zeros_like(a_in)

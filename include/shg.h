@@ -160,12 +160,18 @@ int shg_propagate_batch(int32_t n, shg_plan *const *plans, void *const *a_f,
 size_t shg_batch_workspace_bytes(int32_t n, shg_plan *const *plans);
 
 /* Force launch schedules (used by the autotuner and tests).  row_e / col_e:
- * elements per thread of the row / column transforms (2, 4, 8, 16); row_wg:
- * threads per row-pass block; col_tc: columns per column-pass block.  Zero
- * keeps the current choice.  Errors: SHG_EUNSUPPORTED for a schedule that is
- * not built or does not fit the grid. */
+ * elements per thread of the row / column transforms (4, 8, 16); row_e = 1
+ * selects the wide row pass (one cell per thread for the half-steps, row_wg =
+ * max(256, nx) threads); row_wg: threads per row-pass block; col_tc: columns
+ * per column-pass block.  Zero keeps the current choice.  Errors:
+ * SHG_EUNSUPPORTED for a schedule that is not built or does not fit the grid. */
 int shg_plan_set_schedule(shg_plan *plan, int32_t row_e, int32_t row_wg,
                           int32_t col_e, int32_t col_tc);
+
+/* Same for the schedule a plan uses inside shg_propagate_batch (batches are
+ * throughput bound and default to more elements per thread). */
+int shg_plan_set_batch_schedule(shg_plan *plan, int32_t row_e, int32_t row_wg,
+                                int32_t col_e, int32_t col_tc);
 
 /* Per-kernel timing for measurement.  While enabled, shg_propagate launches
  * every pass individually (no cached graph) with a HIP start/stop event pair

@@ -52,6 +52,7 @@ _SIGS = {
     "shg_plan_set_schedule": (ctypes.c_int, [_VP, _I32, _I32, _I32, _I32]),
     "shg_plan_describe": (ctypes.c_int, [_VP, ctypes.c_char_p, ctypes.c_size_t]),
     "shg_plan_set_timing": (ctypes.c_int, [_VP, _I32]),
+    "shg_plan_set_batch_schedule": (ctypes.c_int, [_VP, _I32, _I32, _I32, _I32]),
     "shg_plan_kernel_times": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double)]),
     "shg_last_error": (ctypes.c_char_p, []),
 }
@@ -161,6 +162,9 @@ class Plan:
 
     def set_schedule(self, row_e=0, row_wg=0, col_e=0, col_tc=0):
         _check(load_library().shg_plan_set_schedule(self.handle, row_e, row_wg, col_e, col_tc))
+
+    def set_batch_schedule(self, row_e=0, row_wg=0, col_e=0, col_tc=0):
+        _check(load_library().shg_plan_set_batch_schedule(self.handle, row_e, row_wg, col_e, col_tc))
 
     def set_timing(self, enable: bool):
         _check(load_library().shg_plan_set_timing(self.handle, 1 if enable else 0))

@@ -35,11 +35,11 @@ bool adj_try(int e, int wg, const RowAdjArgs<R>* a, const RowAdjTArgs<R>* q, hip
     using S = RowShape<G, WG>;
     if (rows_out) *rows_out = S::rows;
     if (a && q) {
-      hipLaunchKernelGGL((row_adj_pass_t<R, N, G, S::rows>), dim3(a->ny / S::rows),
+      hipLaunchKernelGGL((row_adj_pass<R, N, G, S::rows, true>), dim3(a->ny / S::rows),
                          dim3(S::threads), 0, st, *a, *q);
     } else if (a) {
-      hipLaunchKernelGGL((row_adj_pass<R, N, G, S::rows>), dim3(a->ny / S::rows),
-                         dim3(S::threads), 0, st, *a);
+      hipLaunchKernelGGL((row_adj_pass<R, N, G, S::rows, false>), dim3(a->ny / S::rows),
+                         dim3(S::threads), 0, st, *a, RowAdjTArgs<R>{});
     }
     return true;
   } else {
@@ -49,9 +49,31 @@ bool adj_try(int e, int wg, const RowAdjArgs<R>* a, const RowAdjTArgs<R>* q, hip
 }
 
 template <typename R, int N>
+bool adj_wide_try(int e, int wg, const RowAdjArgs<R>* a, const RowAdjTArgs<R>* q, hipStream_t st,
+                  int* rows_out) {
+  using S = WideShape<N>;
+  constexpr size_t lds = (size_t)(6 * S::rows) * padded_len<N>() * sizeof(cx<R>);
+  if constexpr (lds > 64 * 1024) {
+    (void)e; (void)wg; (void)a; (void)q; (void)st; (void)rows_out;
+    return false;
+  } else {
+    if (e != 1 || wg != S::threads) return false;
+    if (rows_out) *rows_out = S::rows;
+    if (a && q) {
+      hipLaunchKernelGGL((row_adj_pass_wide<R, N, true>), dim3(a->ny / S::rows), dim3(S::threads),
+                         0, st, *a, *q);
+    } else if (a) {
+      hipLaunchKernelGGL((row_adj_pass_wide<R, N, false>), dim3(a->ny / S::rows),
+                         dim3(S::threads), 0, st, *a, RowAdjTArgs<R>{});
+    }
+    return true;
+  }
+}
+
+template <typename R, int N>
 bool adj_dispatch_n(int e, int wg, const RowAdjArgs<R>* a, const RowAdjTArgs<R>* q,
                     hipStream_t st, int* rows) {
-  return adj_try<R, N, 4, 64>(e, wg, a, q, st, rows) ||
+  return adj_wide_try<R, N>(e, wg, a, q, st, rows) || adj_try<R, N, 4, 64>(e, wg, a, q, st, rows) ||
          adj_try<R, N, 4, 256>(e, wg, a, q, st, rows) ||
          adj_try<R, N, 8, 64>(e, wg, a, q, st, rows) ||
          adj_try<R, N, 8, 256>(e, wg, a, q, st, rows) ||
@@ -89,7 +111,7 @@ static AdjLayout adj_layout(const Plan& pl) {
   L.segs = (pl.p.nz + L.k - 1) / L.k;
   int rows = 1;
   L.nblk = pl.p.ny;   // upper bound on row-pass blocks
-  if (row_supported(pl, pl.row_e, pl.row_wg, &rows)) L.nblk = pl.p.ny / rows;
+  if (row_supported(pl, pl.adj_e, pl.adj_wg, &rows)) L.nblk = pl.p.ny / rows;
   size_t off = 0;
   L.fwd = off;
   off += align256(forward_ws_bytes(pl));
@@ -220,7 +242,7 @@ static int adjoint_t(Plan& pl, const void* a_f_in, const void* a_sh_in, const do
   }
   auto adj = [&](RowAdjArgs<R>& a, const R* psi, int* rows) {
     q.psi = psi;
-    return adj_dispatch<R>(p.nx, pl.row_e, pl.row_wg, &a, qp, st, rows);
+    return adj_dispatch<R>(p.nx, pl.adj_e, pl.adj_wg, &a, qp, st, rows);
   };
   auto spsi = [&](int s, int b) { return psi_stage + (size_t)(s - b) * n2; };
   int rows = 1;
@@ -248,8 +270,8 @@ static int adjoint_t(Plan& pl, const void* a_f_in, const void* a_sh_in, const do
     ra.gp_first = nullptr;
     ra.gp_second = g2(e - 1);
     if (!adj(ra, spsi(e - 1, b), &rows))
-      return fail(SHG_EUNSUPPORTED, "adjoint row schedule e=%d wg=%d not built", pl.row_e,
-                  pl.row_wg);
+      return fail(SHG_EUNSUPPORTED, "adjoint row schedule e=%d wg=%d not built", pl.adj_e,
+                  pl.adj_wg);
     for (int s = e - 1; s > b; --s) {
       if ((rc = launch_col(pl, la, lb, 1, st))) return rc;
       ra.ua = staged(s - 1, b);

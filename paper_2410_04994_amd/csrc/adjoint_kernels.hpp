@@ -141,83 +141,6 @@ __device__ __forceinline__ void block_sum4(double (&v)[4], double* red) {
   }
 }
 
-// The forward row pass is out = FFT_x(N(IFFT_x(in))).  Both transforms are
-// unnormalised and the DFT matrix is symmetric, so FFT_x^H = IFFT_x and
-// IFFT_x^H = FFT_x: the pull-back applies IFFT_x to the incoming cotangent,
-// pulls it through the two half-steps in reverse order, and applies FFT_x before
-// storing, the same transform sequence as the forward pass.
-template <typename R, int N, int G, int ROWS>
-__global__ void __launch_bounds__(G * ROWS) row_adj_pass(RowAdjArgs<R> p) {
-  constexpr int E = N / G;
-  constexpr int P = padded_len<N>();
-  __shared__ cx<R> lds[ROWS][2][2][P];
-  __shared__ double red[4 * ((G * ROWS + 63) / 64)];
-  const int t = threadIdx.x % G;
-  const int rr = threadIdx.x / G;
-  const int y = blockIdx.x * ROWS + rr;
-  const size_t row = (size_t)y * N;
-  cx<R> va[E], vb[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    va[m] = p.la[row + t + G * m];
-    vb[m] = p.lb[row + t + G * m];
-  }
-  const LdsView<R, 1> a0{&lds[rr][0][0][0]}, a1{&lds[rr][0][1][0]};
-  const LdsView<R, 1> b0{&lds[rr][1][0][0]}, b1{&lds[rr][1][1][0]};
-  if (p.inv_in) {
-    fft_regs<R, N, G, true, 1>(va, a0, a1, t, p.tw);
-    fft_regs<R, N, G, true, 1>(vb, b0, b1, t, p.tw);
-  }
-  const bool und = p.undepleted != 0;
-  const R h = p.h;
-  HalfStep<R> c1{}, c2{};
-  if (p.s_first >= 0) c1 = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks);
-  if (p.s_second >= 0) c2 = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const cx<R> ua = p.ua[row + t + G * m];
-    const cx<R> ub = p.ub[row + t + G * m];
-    cx<R> ya = ua, yb = ub;
-    if (p.s_second >= 0) rk4_cell(ya, yb, c2, p.tf, p.ts, h, und);
-    R g = 0, gt = 0;
-    if (p.s_first >= 0) {
-      rk4_vjp(ya, yb, va[m], vb[m], c1, p.tf, p.ts, h, und, (R)0, g, gt);
-      acc[0] += (double)g;
-      acc[1] += (double)gt;
-    }
-    if (p.s_second >= 0) {
-      g = 0;
-      gt = 0;
-      rk4_vjp(ua, ub, va[m], vb[m], c2, p.tf, p.ts, h, und, h, g, gt);
-      acc[2] += (double)g;
-      acc[3] += (double)gt;
-    }
-  }
-  if (p.fwd_out) {
-    fft_regs<R, N, G, false, 1>(va, a0, a1, t, p.tw);
-    fft_regs<R, N, G, false, 1>(vb, b0, b1, t, p.tw);
-  }
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    p.la[row + t + G * m] = va[m];
-    p.lb[row + t + G * m] = vb[m];
-  }
-  if (p.gp_first || p.gp_second) {
-    block_sum4<G * ROWS>(acc, red);
-    if (threadIdx.x == 0) {
-      if (p.gp_first) {
-        p.gp_first[2 * blockIdx.x] = acc[0];
-        p.gp_first[2 * blockIdx.x + 1] = acc[1];
-      }
-      if (p.gp_second) {
-        p.gp_second[2 * blockIdx.x] = acc[2];
-        p.gp_second[2 * blockIdx.x + 1] = acc[3];
-      }
-    }
-  }
-}
-
 // lambda = g_out + 2 w_j c_j A_j(L): cotangent of the exit fields for the loss
 // Re<g_out, A(L)> + w_F P_F + w_SH P_SH, P_j = c_j sum |A_j|^2.
 template <typename R>
@@ -378,8 +301,105 @@ struct RowAdjTArgs {
   R t_ref, ddk, lens_f, lens_sh, dz;
 };
 
-template <typename R, int N, int G, int ROWS>
-__global__ void __launch_bounds__(G * ROWS) row_adj_pass_t(RowAdjArgs<R> p, RowAdjTArgs<R> q) {
+// Pull-back of one cell through the first half-step of s_first and the second
+// half-step of s_second (either may be absent), from the staged forward state.
+template <typename R, bool TH>
+__device__ __forceinline__ void adj_cell(const RowAdjArgs<R>& p, const RowAdjTArgs<R>& q,
+                                         size_t idx, size_t n2, cx<R>& la, cx<R>& lb,
+                                         double (&acc)[4]) {
+  const bool und = p.undepleted != 0;
+  const R h = p.h;
+  const cx<R> ua = p.ua[idx];
+  const cx<R> ub = p.ub[idx];
+  cx<R> ya = ua, yb = ub;
+  if constexpr (!TH) {
+    HalfStep<R> c1{}, c2{};
+    if (p.s_first >= 0) c1 = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks);
+    if (p.s_second >= 0) {
+      c2 = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);
+      rk4_cell(ya, yb, c2, p.tf, p.ts, h, und);
+    }
+    R g = 0, gt = 0;
+    if (p.s_first >= 0) {
+      rk4_vjp(ya, yb, la, lb, c1, p.tf, p.ts, h, und, (R)0, g, gt);
+      acc[0] += (double)g;
+      acc[1] += (double)gt;
+    }
+    if (p.s_second >= 0) {
+      g = 0;
+      gt = 0;
+      rk4_vjp(ua, ub, la, lb, c2, p.tf, p.ts, h, und, h, g, gt);
+      acc[2] += (double)g;
+      acc[3] += (double)gt;
+    }
+  } else {
+    const R qdz = q.dz * (R)0.25;
+    R psi = q.psi[idx];
+    Carry<R> cr = q.carry[idx];
+    HalfStepT<R> c2{};
+    if (p.s_second >= 0) {
+      const R dT = q.temp[(size_t)p.s_second * n2 + idx] - q.t_ref;
+      c2 = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, q.ddk, psi, dT, h, qdz,
+                         q.lens_f, q.lens_sh);
+      rk4_cell_t(ya, yb, c2, p.tf, p.ts, h, und);
+      psi += dT * q.dz;
+    }
+    if (p.s_first >= 0) {
+      const R dT = q.temp[(size_t)p.s_first * n2 + idx] - q.t_ref;
+      const HalfStepT<R> c1 = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, q.ddk, psi, dT,
+                                            (R)0, qdz, q.lens_f, q.lens_sh);
+      R g = 0, gt = 0, gl = 0;
+      rk4_vjp_t(ya, yb, la, lb, c1, p.tf, p.ts, q.lens_f, q.lens_sh, h, und, (R)0, g, gt, gl);
+      acc[0] += (double)g;
+      acc[1] += (double)gt;
+      // step s_first is complete: its second half-step was pulled back earlier
+      const R g_dk = gt + cr.z + q.dz * cr.x;              // dL/d dk_s for this cell
+      const R g_t = q.ddk * g_dk + gl + cr.w;              // dL/dT_s
+      cr.x += g + cr.y;
+      double* mo = q.moments + 2 * idx;
+      mo[0] += (double)g_t * (double)dT;
+      mo[1] += (double)g_t;
+    }
+    if (p.s_second >= 0) {
+      R g = 0, gt = 0, gl = 0;
+      rk4_vjp_t(ua, ub, la, lb, c2, p.tf, p.ts, q.lens_f, q.lens_sh, h, und, h, g, gt, gl);
+      acc[2] += (double)g;
+      acc[3] += (double)gt;
+      cr.y = g;
+      cr.z = gt;
+      cr.w = gl;
+    } else {
+      cr.y = cr.z = cr.w = (R)0;
+    }
+    q.carry[idx] = cr;
+  }
+}
+
+template <typename R, int T>
+__device__ __forceinline__ void adj_partials(const RowAdjArgs<R>& p, double (&acc)[4], double* red,
+                                             int blk) {
+  if (p.gp_first || p.gp_second) {
+    block_sum4<T>(acc, red);
+    if (threadIdx.x == 0) {
+      if (p.gp_first) {
+        p.gp_first[2 * blk] = acc[0];
+        p.gp_first[2 * blk + 1] = acc[1];
+      }
+      if (p.gp_second) {
+        p.gp_second[2 * blk] = acc[2];
+        p.gp_second[2 * blk + 1] = acc[3];
+      }
+    }
+  }
+}
+
+// The forward row pass is out = FFT_x(N(IFFT_x(in))).  Both transforms are
+// unnormalised and the DFT matrix is symmetric, so FFT_x^H = IFFT_x and
+// IFFT_x^H = FFT_x: the pull-back applies IFFT_x to the incoming cotangent,
+// pulls it through the two half-steps in reverse order, and applies FFT_x before
+// storing, the same transform sequence as the forward pass.
+template <typename R, int N, int G, int ROWS, bool TH>
+__global__ void __launch_bounds__(G * ROWS) row_adj_pass(RowAdjArgs<R> p, RowAdjTArgs<R> q) {
   constexpr int E = N / G;
   constexpr int P = padded_len<N>();
   __shared__ cx<R> lds[ROWS][2][2][P];
@@ -401,55 +421,9 @@ __global__ void __launch_bounds__(G * ROWS) row_adj_pass_t(RowAdjArgs<R> p, RowA
     fft_regs<R, N, G, true, 1>(va, a0, a1, t, p.tw);
     fft_regs<R, N, G, true, 1>(vb, b0, b1, t, p.tw);
   }
-  const bool und = p.undepleted != 0;
-  const R h = p.h;
-  const R qdz = q.dz * (R)0.25;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const size_t idx = row + t + G * m;
-    const cx<R> ua = p.ua[idx];
-    const cx<R> ub = p.ub[idx];
-    R psi = q.psi[idx];
-    Carry<R> cr = q.carry[idx];
-    cx<R> ya = ua, yb = ub;
-    HalfStepT<R> c2{};
-    if (p.s_second >= 0) {
-      const R dT = q.temp[(size_t)p.s_second * n2 + idx] - q.t_ref;
-      c2 = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, q.ddk, psi, dT, h, qdz,
-                         q.lens_f, q.lens_sh);
-      rk4_cell_t(ya, yb, c2, p.tf, p.ts, h, und);
-      psi += dT * q.dz;
-    }
-    if (p.s_first >= 0) {
-      const R dT = q.temp[(size_t)p.s_first * n2 + idx] - q.t_ref;
-      const HalfStepT<R> c1 = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, q.ddk, psi, dT,
-                                            (R)0, qdz, q.lens_f, q.lens_sh);
-      R g = 0, gt = 0, gl = 0;
-      rk4_vjp_t(ya, yb, va[m], vb[m], c1, p.tf, p.ts, q.lens_f, q.lens_sh, h, und, (R)0, g, gt, gl);
-      acc[0] += (double)g;
-      acc[1] += (double)gt;
-      // step s_first is complete: its second half-step was pulled back earlier
-      const R g_dk = gt + cr.z + q.dz * cr.x;              // dL/d dk_s for this cell
-      const R g_t = q.ddk * g_dk + gl + cr.w;              // dL/dT_s
-      cr.x += g + cr.y;
-      double* mo = q.moments + 2 * idx;
-      mo[0] += (double)g_t * (double)dT;
-      mo[1] += (double)g_t;
-    }
-    if (p.s_second >= 0) {
-      R g = 0, gt = 0, gl = 0;
-      rk4_vjp_t(ua, ub, va[m], vb[m], c2, p.tf, p.ts, q.lens_f, q.lens_sh, h, und, h, g, gt, gl);
-      acc[2] += (double)g;
-      acc[3] += (double)gt;
-      cr.y = g;
-      cr.z = gt;
-      cr.w = gl;
-    } else {
-      cr.y = cr.z = cr.w = (R)0;
-    }
-    q.carry[idx] = cr;
-  }
+  for (int m = 0; m < E; ++m) adj_cell<R, TH>(p, q, row + t + G * m, n2, va[m], vb[m], acc);
   if (p.fwd_out) {
     fft_regs<R, N, G, false, 1>(va, a0, a1, t, p.tw);
     fft_regs<R, N, G, false, 1>(vb, b0, b1, t, p.tw);
@@ -459,19 +433,72 @@ __global__ void __launch_bounds__(G * ROWS) row_adj_pass_t(RowAdjArgs<R> p, RowA
     p.la[row + t + G * m] = va[m];
     p.lb[row + t + G * m] = vb[m];
   }
-  if (p.gp_first || p.gp_second) {
-    block_sum4<G * ROWS>(acc, red);
-    if (threadIdx.x == 0) {
-      if (p.gp_first) {
-        p.gp_first[2 * blockIdx.x] = acc[0];
-        p.gp_first[2 * blockIdx.x + 1] = acc[1];
-      }
-      if (p.gp_second) {
-        p.gp_second[2 * blockIdx.x] = acc[2];
-        p.gp_second[2 * blockIdx.x + 1] = acc[3];
-      }
+  adj_partials<R, G * ROWS>(p, acc, red, blockIdx.x);
+}
+
+// Wide variant (one cell per thread for the pull-back; see row_wide_body).
+template <typename R, int N, bool TH>
+__global__ void __launch_bounds__(WideShape<N>::threads) row_adj_pass_wide(RowAdjArgs<R> p,
+                                                                            RowAdjTArgs<R> q) {
+  using S = WideShape<N>;
+  constexpr int ROWS = S::rows, G = S::g, EF = S::ef;
+  constexpr int P = padded_len<N>();
+  __shared__ cx<R> cell[2][ROWS][P];
+  __shared__ cx<R> pp[2 * ROWS][2][P];
+  __shared__ double red[4 * ((S::threads + 63) / 64)];
+  const int blk = blockIdx.x;
+  const int tid = threadIdx.x;
+  const bool fth = tid < S::fft_threads;
+  const int tr = fth ? tid / G : 0;
+  const int t = tid % G;
+  const int ff = tr & 1, fr = tr >> 1;
+  const size_t frow = (size_t)(blk * ROWS + fr) * N;
+  const LdsView<R, 1> q0{&pp[tr][0][0]}, q1{&pp[tr][1][0]};
+  const int cr = tid / N, cxi = tid % N;
+  const size_t idx = (size_t)(blk * ROWS + cr) * N + cxi;
+  const size_t n2 = (size_t)p.ny * N;
+  cx<R> v[EF];
+  cx<R> la, lb;
+  if (p.inv_in) {
+    if (fth) {
+      const cx<R>* src = ff ? p.lb : p.la;
+#pragma unroll
+      for (int m = 0; m < EF; ++m) v[m] = src[frow + t + G * m];
     }
+    fft_regs<R, N, G, true, 1>(v, q0, q1, t, p.tw, fth);
+    if (fth) {
+#pragma unroll
+      for (int m = 0; m < EF; ++m) cell[ff][fr][pad16(t + G * m)] = v[m];
+    }
+    __syncthreads();
+    la = cell[0][cr][pad16(cxi)];
+    lb = cell[1][cr][pad16(cxi)];
+  } else {
+    la = p.la[idx];
+    lb = p.lb[idx];
   }
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  adj_cell<R, TH>(p, q, idx, n2, la, lb, acc);
+  if (p.fwd_out) {
+    __syncthreads();
+    cell[0][cr][pad16(cxi)] = la;
+    cell[1][cr][pad16(cxi)] = lb;
+    __syncthreads();
+    if (fth) {
+#pragma unroll
+      for (int m = 0; m < EF; ++m) v[m] = cell[ff][fr][pad16(t + G * m)];
+    }
+    fft_regs<R, N, G, false, 1>(v, q0, q1, t, p.tw, fth);
+    if (fth) {
+      cx<R>* dst = ff ? p.lb : p.la;
+#pragma unroll
+      for (int m = 0; m < EF; ++m) dst[frow + t + G * m] = v[m];
+    }
+  } else {
+    p.la[idx] = la;
+    p.lb[idx] = lb;
+  }
+  adj_partials<R, S::threads>(p, acc, red, blk);
 }
 
 template <typename R>

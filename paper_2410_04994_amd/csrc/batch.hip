@@ -70,8 +70,24 @@ bool bcol_try(int e, int tc, const BatchInst<R>* d, int count, int blocks, hipSt
 }
 
 template <typename R, int N>
+bool brow_wide_try(int e, int wg, const BatchInst<R>* d, int count, int s, int blocks,
+                   hipStream_t st) {
+  using S = WideShape<N>;
+  constexpr size_t lds = (size_t)(6 * S::rows) * padded_len<N>() * sizeof(cx<R>);
+  if constexpr (lds > 64 * 1024) {
+    (void)e; (void)wg; (void)d; (void)count; (void)s; (void)blocks; (void)st;
+    return false;
+  } else {
+    if (e != 1 || wg != S::threads) return false;
+    hipLaunchKernelGGL((row_pass_batch_wide<R, N>), dim3(blocks, count), dim3(S::threads), 0, st,
+                       d, s);
+    return true;
+  }
+}
+
+template <typename R, int N>
 bool brow_n(int e, int wg, const BatchInst<R>* d, int c, int s, int b, hipStream_t st) {
-  return brow_try<R, N, 4, 64>(e, wg, d, c, s, b, st) ||
+  return brow_wide_try<R, N>(e, wg, d, c, s, b, st) || brow_try<R, N, 4, 64>(e, wg, d, c, s, b, st) ||
          brow_try<R, N, 4, 256>(e, wg, d, c, s, b, st) ||
          brow_try<R, N, 8, 64>(e, wg, d, c, s, b, st) ||
          brow_try<R, N, 8, 256>(e, wg, d, c, s, b, st) ||
@@ -142,7 +158,8 @@ static int build_info(int n, shg_plan* const* plans, BatchPlanInfo& bi) {
   std::map<std::tuple<int, int, int, int, int, int>, std::vector<int>> by;
   for (int i = 0; i < n; ++i) {
     const Plan& pl = *reinterpret_cast<const Plan*>(plans[i]);
-    by[std::make_tuple(pl.p.nx, pl.p.ny, pl.row_e, pl.row_wg, pl.col_e, pl.col_tc)].push_back(i);
+    by[std::make_tuple(pl.p.nx, pl.p.ny, pl.b_row_e, pl.b_row_wg, pl.b_col_e, pl.b_col_tc)]
+        .push_back(i);
   }
   const Plan& p0 = *reinterpret_cast<const Plan*>(plans[0]);
   const size_t csize = 2 * (size_t)p0.real_bytes;
@@ -229,7 +246,7 @@ static int enqueue_batch(int n, shg_plan* const* plans, void* const* a_f, void* 
         c.my[w] = pl.my[w];
       }
       c.nx = pl.p.nx;
-      c.tiles = pl.p.nx / pl.col_tc;
+      c.tiles = pl.p.nx / pl.b_col_tc;
       c.conj_prop = 0;
       I.dk_z = dk_z ? dk_z[i] : nullptr;
       I.dk0 = pl.p.dk0;
@@ -239,7 +256,9 @@ static int enqueue_batch(int n, shg_plan* const* plans, void* const* a_f, void* 
       I.partials = (double*)(ws + bi.part_at[i]);
       I.powers = powers ? powers + 2 * i : nullptr;
       I.nz = pl.p.nz;
-      I.row_blocks = pl.p.ny / pl.row_rows;
+      int brows = 1;
+      row_supported(pl, pl.b_row_e, pl.b_row_wg, &brows);
+      I.row_blocks = pl.p.ny / brows;
     }
     hipError_t e = hipMemcpyAsync(dev, host.data(), sizeof(BatchInst<R>) * n,
                                   hipMemcpyHostToDevice, st);
@@ -320,8 +339,8 @@ static int propagate_batch(int n, shg_plan* const* plans, void* const* a_f, void
     key.push_back(a_f[i]);
     key.push_back(a_sh[i]);
     key.push_back(dk_z ? dk_z[i] : nullptr);
-    key.push_back(reinterpret_cast<const void*>((uintptr_t)(pl->row_e * 1000000 + pl->row_wg * 1000 +
-                                                            pl->col_e * 100 + pl->col_tc)));
+    key.push_back(reinterpret_cast<const void*>(
+        (uintptr_t)(pl->b_row_e * 1000000 + pl->b_row_wg * 1000 + pl->b_col_e * 100 + pl->b_col_tc)));
   }
   key.push_back(ws);
   key.push_back(powers);

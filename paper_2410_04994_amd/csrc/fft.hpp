@@ -251,13 +251,13 @@ struct LdsView {
 template <typename R, int N, int G, bool INV, int NS, int REM, bool FIRST, int STRIDE>
 __device__ __forceinline__ void stockham(cx<R> (&v)[N / G], LdsView<R, STRIDE> in,
                                          LdsView<R, STRIDE> out, int t,
-                                         const Tw<R>* __restrict__ tw) {
+                                         const Tw<R>* __restrict__ tw, bool active) {
   constexpr int E = N / G;
   constexpr int RP = pick_radix<E, REM>::value;
   constexpr int NB = E / RP;
   constexpr bool LAST = (REM == RP);
 #pragma unroll
-  for (int u = 0; u < NB; ++u) {
+  for (int u = 0; u < NB && active; ++u) {
     const int j = t + G * u;
     cx<R> x[RP];
 #pragma unroll
@@ -282,18 +282,19 @@ __device__ __forceinline__ void stockham(cx<R> (&v)[N / G], LdsView<R, STRIDE> i
   }
   if constexpr (!LAST) {
     __syncthreads();
-    stockham<R, N, G, INV, NS * RP, REM / RP, false, STRIDE>(v, out, in, t, tw);
+    stockham<R, N, G, INV, NS * RP, REM / RP, false, STRIDE>(v, out, in, t, tw, active);
   }
 }
 
 // Whole transform of the registers v.  All threads of the block must call it
 // (it contains block barriers); one leading barrier protects LDS reuse.
+// Threads with active = false only take part in the barriers.
 template <typename R, int N, int G, bool INV, int STRIDE>
 __device__ __forceinline__ void fft_regs(cx<R> (&v)[N / G], LdsView<R, STRIDE> b0,
                                          LdsView<R, STRIDE> b1, int t,
-                                         const Tw<R>* __restrict__ tw) {
+                                         const Tw<R>* __restrict__ tw, bool active = true) {
   if constexpr (pick_radix<N / G, N>::value < N) __syncthreads();
-  stockham<R, N, G, INV, 1, N, true, STRIDE>(v, b0, b1, t, tw);
+  stockham<R, N, G, INV, 1, N, true, STRIDE>(v, b0, b1, t, tw, active);
 }
 
 }  // namespace shg

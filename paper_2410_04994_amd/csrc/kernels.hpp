@@ -303,6 +303,130 @@ __global__ void __launch_bounds__(256) psi_init(const R* __restrict__ temp, int 
   psi[i] = (R)acc;
 }
 
+// ---------------------------------------------------------------- wide row pass
+// Latency-oriented row pass for marches that are too small to fill the chip:
+// every thread owns one cell (both fields) for the two RK4 half-steps, and the
+// first half of the block runs the row transforms at 4 elements per thread
+// (2 * ROWS transforms of length N).  Cells move between the transform layout
+// and the one-cell-per-thread layout through LDS.  Same arithmetic, in the same
+// order per cell, as row_body.
+template <int N>
+struct WideShape {
+  static constexpr int threads = N >= 256 ? N : 256;
+  static constexpr int rows = threads / N;
+  static constexpr int ef = 4;
+  static constexpr int g = N / ef;
+  static constexpr int fft_threads = 2 * rows * g;
+};
+
+template <typename R, int N, bool TH>
+__device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
+  using S = WideShape<N>;
+  constexpr int ROWS = S::rows, G = S::g, EF = S::ef;
+  constexpr int P = padded_len<N>();
+  __shared__ cx<R> cell[2][ROWS][P];
+  __shared__ cx<R> pp[2 * ROWS][2][P];
+  __shared__ double red[2 * ((S::threads + 63) / 64)];
+  const int tid = threadIdx.x;
+  // transform role: transform tr = 2 * row + field, element t + G*m
+  const bool fth = tid < S::fft_threads;
+  const int tr = fth ? tid / G : 0;
+  const int t = tid % G;
+  const int ff = tr & 1, fr = tr >> 1;
+  const size_t frow = (size_t)(blk * ROWS + fr) * N;
+  const LdsView<R, 1> q0{&pp[tr][0][0]}, q1{&pp[tr][1][0]};
+  // cell role
+  const int cr = tid / N, cxi = tid % N;
+  const size_t idx = (size_t)(blk * ROWS + cr) * N + cxi;
+  cx<R> v[EF];
+  cx<R> a, b;
+  if (p.inv_in) {
+    if (fth) {
+      const cx<R>* src = ff ? p.bin : p.ain;
+#pragma unroll
+      for (int m = 0; m < EF; ++m) v[m] = src[frow + t + G * m];
+    }
+    fft_regs<R, N, G, true, 1>(v, q0, q1, t, p.tw, fth);
+    if (fth) {
+#pragma unroll
+      for (int m = 0; m < EF; ++m) cell[ff][fr][pad16(t + G * m)] = v[m];
+    }
+    __syncthreads();
+    a = cell[0][cr][pad16(cxi)];
+    b = cell[1][cr][pad16(cxi)];
+  } else {
+    a = p.ain[idx];
+    b = p.bin[idx];
+  }
+  if (p.tap_a) {
+    p.tap_a[idx] = a;
+    p.tap_b[idx] = b;
+  }
+  const bool und = p.undepleted != 0;
+  if constexpr (TH) {
+    const size_t n2 = (size_t)p.ny * N;
+    const R qdz = p.dz * (R)0.25;
+    R psi = p.psi[idx];
+    if (p.tap_psi) p.tap_psi[idx] = psi;
+    if (p.s_second >= 0) {
+      const R dT = p.temp[(size_t)p.s_second * n2 + idx] - p.t_ref;
+      const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, p.ddk, psi,
+                                           dT, p.h, qdz, p.lens_f, p.lens_sh);
+      rk4_cell_t(a, b, c, p.tf, p.ts, p.h, und);
+      psi += dT * p.dz;
+    }
+    if (p.s_first >= 0) {
+      const R dT = p.temp[(size_t)p.s_first * n2 + idx] - p.t_ref;
+      const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, p.ddk, psi, dT,
+                                           (R)0, qdz, p.lens_f, p.lens_sh);
+      rk4_cell_t(a, b, c, p.tf, p.ts, p.h, und);
+    }
+    if (p.s_second >= 0) p.psi[idx] = psi;
+  } else {
+    if (p.s_second >= 0) {
+      const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);
+      rk4_cell(a, b, c, p.tf, p.ts, p.h, und);
+    }
+    if (p.s_first >= 0) {
+      const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks);
+      rk4_cell(a, b, c, p.tf, p.ts, p.h, und);
+    }
+  }
+  if (p.fwd_out) {
+    __syncthreads();   // every thread has read its cell before it is overwritten
+    cell[0][cr][pad16(cxi)] = a;
+    cell[1][cr][pad16(cxi)] = b;
+    __syncthreads();
+    if (fth) {
+#pragma unroll
+      for (int m = 0; m < EF; ++m) v[m] = cell[ff][fr][pad16(t + G * m)];
+    }
+    fft_regs<R, N, G, false, 1>(v, q0, q1, t, p.tw, fth);
+    if (fth) {
+      cx<R>* dst = ff ? p.bout : p.aout;
+#pragma unroll
+      for (int m = 0; m < EF; ++m) dst[frow + t + G * m] = v[m];
+    }
+  } else {
+    p.aout[idx] = a;
+    p.bout[idx] = b;
+  }
+  if (p.partials) {
+    double sa = (double)a.re * (double)a.re + (double)a.im * (double)a.im;
+    double sb = (double)b.re * (double)b.re + (double)b.im * (double)b.im;
+    block_sum2<S::threads>(sa, sb, red);
+    if (threadIdx.x == 0) {
+      p.partials[2 * blk] = sa;
+      p.partials[2 * blk + 1] = sb;
+    }
+  }
+}
+
+template <typename R, int N, bool TH>
+__global__ void __launch_bounds__(WideShape<N>::threads) row_pass_wide(RowArgs<R> p) {
+  row_wide_body<R, N, TH>(p, blockIdx.x);
+}
+
 // ---------------------------------------------------------------- column pass
 template <typename R>
 struct ColArgs {
@@ -461,6 +585,20 @@ __global__ void __launch_bounds__(G * ROWS) row_pass_batch(const BatchInst<R>* _
   p.fwd_out = s < nz ? 1 : 0;
   p.partials = (s == nz && I.powers) ? I.partials : nullptr;
   row_body<R, N, G, ROWS>(p, blockIdx.x);
+}
+
+template <typename R, int N>
+__global__ void __launch_bounds__(WideShape<N>::threads) row_pass_batch_wide(
+    const BatchInst<R>* __restrict__ inst, int s) {
+  const BatchInst<R>& I = inst[blockIdx.y];
+  RowArgs<R> p = I.row;
+  const int nz = I.nz;
+  p.s_second = s >= 1 ? s - 1 : -1;
+  p.s_first = s < nz ? s : -1;
+  p.inv_in = s >= 1 ? 1 : 0;
+  p.fwd_out = s < nz ? 1 : 0;
+  p.partials = (s == nz && I.powers) ? I.partials : nullptr;
+  row_wide_body<R, N, false>(p, blockIdx.x);
 }
 
 template <typename R, int N, int G, int TC>

@@ -46,6 +46,8 @@ struct Plan {
   double* my[2] = {nullptr, nullptr};
   // schedule
   int row_e = 0, row_wg = 0, row_rows = 1;
+  int adj_e = 0, adj_wg = 0;     // adjoint row pass
+  int b_row_e = 0, b_row_wg = 0, b_col_e = 0, b_col_tc = 1;   // schedule inside batches
   int col_e = 0, col_tc = 1;
   // library-owned workspaces
   void* own_ws = nullptr;

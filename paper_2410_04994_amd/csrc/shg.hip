@@ -135,10 +135,33 @@ bool col_try(int e, int tc, const ColArgs<R>* a, hipStream_t st, LaunchTimer* tm
   }
 }
 
+// Wide schedule: e = 1 (one cell per thread), wg = WideShape<N>::threads.
+template <typename R, int N>
+bool row_wide_try(int e, int wg, const RowArgs<R>* a, hipStream_t st, int* rows_out,
+                  LaunchTimer* tm) {
+  using S = WideShape<N>;
+  constexpr size_t lds = (size_t)(2 * S::rows + 4 * S::rows) * padded_len<N>() * sizeof(cx<R>);
+  if constexpr (lds > 64 * 1024) {
+    (void)e; (void)wg; (void)a; (void)st; (void)rows_out; (void)tm;
+    return false;
+  } else {
+    if (e != 1 || wg != S::threads) return false;
+    if (rows_out) *rows_out = S::rows;
+    if (a) {
+      if (a->temp)
+        launch(row_pass_wide<R, N, true>, dim3(a->ny / S::rows), dim3(S::threads), st, tm, 0, *a);
+      else
+        launch(row_pass_wide<R, N, false>, dim3(a->ny / S::rows), dim3(S::threads), st, tm, 0,
+               *a);
+    }
+    return true;
+  }
+}
+
 template <typename R, int N>
 bool row_dispatch_n(int e, int wg, const RowArgs<R>* a, hipStream_t st, int* rows,
                     LaunchTimer* tm) {
-  return row_try<R, N, 4, 64>(e, wg, a, st, rows, tm) ||
+  return row_wide_try<R, N>(e, wg, a, st, rows, tm) || row_try<R, N, 4, 64>(e, wg, a, st, rows, tm) ||
          row_try<R, N, 4, 256>(e, wg, a, st, rows, tm) ||
          row_try<R, N, 8, 64>(e, wg, a, st, rows, tm) ||
          row_try<R, N, 8, 256>(e, wg, a, st, rows, tm) ||
@@ -202,38 +225,72 @@ bool col_supported(const Plan& pl, int e, int tc) {
   return okk && pl.p.nx % tc == 0;
 }
 
-// Default schedules: spread a single instance over many blocks (it is latency
-// bound), keep 64-thread blocks.  The autotuner may override.
+// Default schedules, from on-device sweeps of every built schedule.
+// Single instance (latency bound): the wide row pass (one cell per thread) and
+// a column pass with few elements per thread.  Batches (throughput bound):
+// more elements per thread, fewer LDS round trips.  The autotuner may override
+// both.
+struct SchedRow {
+  int n;
+  int re, rw, ce, ct;
+};
+static const SchedRow kSingle[] = {{16, 1, 256, 4, 16}, {32, 1, 256, 4, 8}, {64, 1, 256, 4, 4},
+                                   {128, 1, 256, 4, 2}, {256, 1, 256, 4, 2}, {512, 1, 512, 8, 4}};
+static const SchedRow kBatch[] = {{16, 4, 64, 4, 16}, {32, 4, 64, 4, 16}, {64, 4, 64, 8, 8},
+                                  {128, 8, 64, 16, 8}, {256, 8, 64, 16, 4}, {512, 8, 64, 16, 4}};
+
+static bool apply_row(Plan& pl, int re, int rw, int* rows) { return row_supported(pl, re, rw, rows); }
+
+static void pick(Plan& pl, const SchedRow* table, int* re, int* rw, int* ce, int* ct) {
+  *re = *rw = *ce = *ct = 0;
+  for (int i = 0; i < 6; ++i) {
+    if (table[i].n == pl.p.nx) {
+      int rows;
+      if (apply_row(pl, table[i].re, table[i].rw, &rows)) {
+        *re = table[i].re;
+        *rw = table[i].rw;
+      }
+    }
+    if (table[i].n == pl.p.ny) {
+      int tc = table[i].ct;
+      while (tc > 1 && !col_supported(pl, table[i].ce, tc)) tc >>= 1;
+      if (col_supported(pl, table[i].ce, tc)) {
+        *ce = table[i].ce;
+        *ct = tc;
+      }
+    }
+  }
+  // fall back to any built schedule
+  const int es[] = {4, 8, 16};
+  const int wgs[] = {64, 256};
+  for (int e : es)
+    for (int w : wgs) {
+      int rows;
+      if (!*re && row_supported(pl, e, w, &rows)) {
+        *re = e;
+        *rw = w;
+      }
+    }
+  for (int e : es)
+    for (int tc = 16; tc >= 1 && !*ce; tc >>= 1)
+      if (col_supported(pl, e, tc)) {
+        *ce = e;
+        *ct = tc;
+      }
+}
+
+// The adjoint row pass follows the single-instance row schedule (it has a wide
+// variant too); row_supported covers both since they share shapes.
+static void pick_adjoint(Plan& pl) {
+  pl.adj_e = pl.row_e;
+  pl.adj_wg = pl.row_wg;
+}
+
 void default_schedule(Plan& pl) {
-  const int nx = pl.p.nx, ny = pl.p.ny;
-  const int row_e[] = {8, 4, 16};
-  for (int e : row_e) {
-    if (row_supported(pl, e, 64, &pl.row_rows)) {
-      pl.row_e = e;
-      pl.row_wg = 64;
-      break;
-    }
-  }
-  const int col_e[] = {8, 4, 16};
-  pl.col_e = 0;
-  for (int e : col_e) {
-    if (e > ny) continue;
-    const int g = ny / e;
-    int tc = 64 / g;
-    if (tc < 1) tc = 1;
-    if (tc > 16) tc = 16;
-    while (tc > 1 && nx % tc) tc >>= 1;
-    if (col_supported(pl, e, tc)) {
-      pl.col_e = e;
-      pl.col_tc = tc;
-      break;
-    }
-    if (col_supported(pl, e, 2 * tc)) {
-      pl.col_e = e;
-      pl.col_tc = 2 * tc;
-      break;
-    }
-  }
+  pick(pl, kSingle, &pl.row_e, &pl.row_wg, &pl.col_e, &pl.col_tc);
+  row_supported(pl, pl.row_e, pl.row_wg, &pl.row_rows);
+  pick(pl, kBatch, &pl.b_row_e, &pl.b_row_wg, &pl.b_col_e, &pl.b_col_tc);
+  pick_adjoint(pl);
 }
 
 // ---------------------------------------------------------------- tables
@@ -694,8 +751,31 @@ int shg_plan_set_schedule(shg_plan* plan, int32_t row_e, int32_t row_wg, int32_t
   pl->row_e = re;
   pl->row_wg = rw;
   pl->row_rows = rows;
+  pl->adj_e = re;
+  pl->adj_wg = rw;
   pl->col_e = ce;
   pl->col_tc = ct;
+  return ok();
+}
+
+int shg_plan_set_batch_schedule(shg_plan* plan, int32_t row_e, int32_t row_wg, int32_t col_e,
+                                int32_t col_tc) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  Plan* pl = reinterpret_cast<Plan*>(plan);
+  const int re = row_e ? row_e : pl->b_row_e, rw = row_wg ? row_wg : pl->b_row_wg;
+  const int ce = col_e ? col_e : pl->b_col_e, ct = col_tc ? col_tc : pl->b_col_tc;
+  int rows = 0;
+  if (!row_supported(*pl, re, rw, &rows))
+    return fail(SHG_EUNSUPPORTED, "row schedule e=%d wg=%d not built for nx=%d ny=%d", re, rw,
+                pl->p.nx, pl->p.ny);
+  if (!col_supported(*pl, ce, ct))
+    return fail(SHG_EUNSUPPORTED, "column schedule e=%d tc=%d not built for nx=%d ny=%d", ce, ct,
+                pl->p.nx, pl->p.ny);
+  pl->b_row_e = re;
+  pl->b_row_wg = rw;
+  pl->b_col_e = ce;
+  pl->b_col_tc = ct;
   return ok();
 }
 
@@ -705,9 +785,11 @@ int shg_plan_describe(const shg_plan* plan, char* buf, size_t len) {
   const Plan* pl = reinterpret_cast<const Plan*>(plan);
   if (buf && len) {
     snprintf(buf, len,
-             "dtype=%s nx=%d ny=%d nz=%d row(e=%d wg=%d rows=%d) col(e=%d tc=%d) graph=%d",
+             "dtype=%s nx=%d ny=%d nz=%d row(e=%d wg=%d rows=%d) adj(e=%d wg=%d) col(e=%d tc=%d) "
+             "batch(row e=%d wg=%d col e=%d tc=%d) graph=%d",
              pl->dtype == SHG_C64 ? "c64" : "c128", pl->p.nx, pl->p.ny, pl->p.nz, pl->row_e,
-             pl->row_wg, pl->row_rows, pl->col_e, pl->col_tc,
+             pl->row_wg, pl->row_rows, pl->adj_e, pl->adj_wg, pl->col_e, pl->col_tc, pl->b_row_e,
+             pl->b_row_wg, pl->b_col_e, pl->b_col_tc,
              (pl->p.flags & SHG_NO_GRAPH) ? 0 : 1);
   }
   return ok();

@@ -18,9 +18,10 @@ def _timed(fn, reps, torch):
 def batched(device, reps=3):
     import torch
     import workloads
-    from paper_2410_04994_amd import Plan, propagate_batch, beams
+    from paper_2410_04994_amd import Plan, propagate_batch, beams, autotune
     wls = workloads.c3_batch()
     plans = [Plan(w.params(), "c64") for w in wls]
+    autotune.tune_batch(plans)
     a_in = [beams.pump_for(w, dtype=torch.complex64, device=device) for w in wls]
     a = [x.clone() for x in a_in]
     b = [torch.zeros_like(x) for x in a_in]
@@ -36,7 +37,8 @@ def batched(device, reps=3):
     run()
     sec = _timed(run, reps, torch)
     cells = sum(w.cell_steps for w in wls)
-    return {"workload": "c3_batch_512_mixed_64_128_256", "instances": len(wls),
+    scheds = sorted({p.describe().split("batch(")[1].split(")")[0] for p in plans})
+    return {"workload": "c3_batch_512_mixed_64_128_256", "instances": len(wls), "schedules": scheds,
             "cell_steps": cells, "ms_per_sweep": round(sec * 1e3, 3),
             "cell_steps_per_s": round(cells / sec, 1),
             "frac_hbm_at_64B": round(cells / sec * 64 / 8e12, 4)}
@@ -45,9 +47,10 @@ def batched(device, reps=3):
 def fwd_adj(device, reps=2):
     import torch
     import workloads
-    from paper_2410_04994_amd import Plan, beams
+    from paper_2410_04994_amd import Plan, beams, autotune
     wl = workloads.c4_diff_c64()
     plan = Plan(wl.params(), "c64", checkpoint_every=32)
+    autotune.tune_single(plan)
     theta = torch.from_numpy(workloads.phase_noise(wl)).to(device)
     a0 = beams.pump_for(wl, theta=theta, dtype=torch.complex64, device=device)
     b0 = torch.zeros_like(a0)

@@ -39,12 +39,41 @@ def run_batch(wls, dtype="c64", dk=None):
     return plans, ins, [x.cpu().numpy() for x in a], [x.cpu().numpy() for x in b], pw.cpu().numpy()
 
 
+def test_wide_batch_schedule_matches_narrow():
+    """The wide row pass inside batches gives the same instances as the
+    narrow one to rounding."""
+    wls = small_batch(n=6, seed=11, max_nz=12)
+    from paper_2410_04994_amd import Plan, propagate_batch
+    outs = []
+    for sched in ((1, 256, 4, 4), None):
+        plans = [Plan(w.params(), "c64") for w in wls]
+        if sched:
+            for p in plans:
+                p.set_batch_schedule(*sched)
+        ins = [inputs(w) for w in wls]
+        a = [torch.from_numpy(x[0]).cuda() for x in ins]
+        b = [torch.from_numpy(x[1]).cuda() for x in ins]
+        propagate_batch(plans, a, b)
+        torch.cuda.synchronize()
+        outs.append([x.cpu().numpy() for x in b])
+    for x, y in zip(*outs):
+        assert rel(x, y) < 1e-5
+
+
+def batch_schedule(plan):
+    """(row_e, row_wg, col_e, col_tc) the plan uses inside batches."""
+    import re
+    m = re.search(r"batch\(row e=(\d+) wg=(\d+) col e=(\d+) tc=(\d+)\)", plan.describe())
+    return tuple(int(x) for x in m.groups())
+
+
 def test_batch_equals_single_instance_runs_bitwise():
     from paper_2410_04994_amd import Plan
     wls = small_batch()
     plans, ins, A, B, pw = run_batch(wls)
     for i, w in enumerate(wls):
         p = Plan(w.params(), "c64")
+        p.set_schedule(*batch_schedule(plans[i]))
         a = torch.from_numpy(ins[i][0]).cuda()
         b = torch.from_numpy(ins[i][1]).cuda()
         pp = p.propagate(a, b)
@@ -99,6 +128,7 @@ def test_mixed_size_sweep_sampled_against_oracle():
     for i in rng.choice(len(wls), size=24, replace=False):
         w = wls[i]
         p = Plan(w.params(), "c64")
+        p.set_schedule(*batch_schedule(plans[i]))
         a = torch.from_numpy(ins[i][0]).cuda()
         b = torch.from_numpy(ins[i][1]).cuda()
         p.propagate(a, b)
