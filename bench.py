@@ -84,6 +84,9 @@ def main(argv=None):
     ap.add_argument("--cpu-sample-steps", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 64 MiB device copy from a cache-cold source "
+                         "(reference for the HBM byte counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -117,6 +120,15 @@ def main(argv=None):
         b.copy_(b_in)
         plan.propagate(a, b, workspace=ws, powers=powers, stream=stream)
 
+    if args.calibrate_copy:
+        src = torch.ones(16 << 20, dtype=torch.float32, device=dev)      # 64 MiB
+        dst = torch.empty_like(src)
+        evict = torch.ones(128 << 20, dtype=torch.float32, device=dev)   # 512 MiB > L2 + MALL
+        evict.add_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst, evict
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

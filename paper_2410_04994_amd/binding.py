@@ -67,6 +67,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library {path} is missing: run `python -m paper_2410_04994_amd.build`")
+    # torch ships its own HIP runtime; loading it first makes libshg bind to
+    # that same runtime (one runtime per process, shared streams and memory)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
