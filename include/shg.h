@@ -78,7 +78,8 @@ typedef struct {
   double dn_dT;           /* thermo-optic coefficient [1/K], both waves        */
   double t_ref;           /* reference temperature [K]                         */
   uint32_t flags;         /* SHG_UNDEPLETED | SHG_NO_GRAPH                      */
-  int32_t checkpoint_every; /* adjoint checkpoint interval K (0 -> 32)         */
+  int32_t checkpoint_every; /* adjoint checkpoint interval K (0 -> automatic:  */
+                            /* K = nz when nz staged steps fit in 4 GiB)       */
 } shg_params;
 
 /* Create a plan: validates the parameters, builds the FP64 propagator and
@@ -129,7 +130,9 @@ int shg_propagate(shg_plan *plan, void *a_f, void *a_sh, const double *dk_z,
  *   a_f_out, a_sh_out  out: forward fields at z = L, or NULL
  *   powers             out: double[2] forward exit powers, or NULL
  *   workspace          shg_workspace_bytes(plan, 1) bytes (required)
- * Fields are checkpointed every params.checkpoint_every steps and recomputed.
+ * Fields are checkpointed every K = params.checkpoint_every steps; the
+ * backward sweep recomputes every segment except the last one, which the
+ * forward sweep stages directly (K = nz recomputes nothing).
  * Errors: as shg_propagate; SHG_EINVAL also for a NULL workspace. */
 int shg_propagate_adjoint(shg_plan *plan, const void *a_f_in, const void *a_sh_in,
                           const double *dk_z, const void *temp,

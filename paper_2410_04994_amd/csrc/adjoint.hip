@@ -192,13 +192,16 @@ static int adjoint_t(Plan& pl, const void* a_f_in, const void* a_sh_in, const do
     const void *ia, *ib;
     seg_in(k, &ia, &ib);
     const bool last = (k == L.segs - 1);
+    // the last segment stages its states now, so the backward sweep starts
+    // without recomputing it
     FwdIO io{ia, ib, work, work + n2, last ? (void*)fin_a : (void*)ck(k + 1),
-             last ? (void*)fin_b : (void*)(ck(k + 1) + n2), nullptr};
+             last ? (void*)fin_b : (void*)(ck(k + 1) + n2), last ? stage : nullptr};
     if (th) {
       hipLaunchKernelGGL((copy_real<R>), dim3(nb), dim3(256), 0, st, (const R*)psi_work,
                          psi_ck(k), n2);
       io.temp = temp;
       io.psi = psi_work;
+      io.tap_psi = last ? psi_stage : nullptr;
     }
     rc = enqueue_forward_io(pl, io, dk_z, b, e, fws, last ? powers : nullptr, st, k == 0);
     if (rc) return rc;
@@ -250,16 +253,18 @@ static int adjoint_t(Plan& pl, const void* a_f_in, const void* a_sh_in, const do
     const int b = k * L.k, e = std::min(p.nz, b + L.k);
     const void *ia, *ib;
     seg_in(k, &ia, &ib);
-    FwdIO io{ia, ib, work, work + n2, work, work + n2, stage};
-    if (th) {
-      hipLaunchKernelGGL((copy_real<R>), dim3(nb), dim3(256), 0, st, (const R*)psi_ck(k),
-                         psi_work, n2);
-      io.temp = temp;
-      io.psi = psi_work;
-      io.tap_psi = psi_stage;
+    if (k < L.segs - 1) {   // recompute the segment's states from its checkpoint
+      FwdIO io{ia, ib, work, work + n2, work, work + n2, stage};
+      if (th) {
+        hipLaunchKernelGGL((copy_real<R>), dim3(nb), dim3(256), 0, st, (const R*)psi_ck(k),
+                           psi_work, n2);
+        io.temp = temp;
+        io.psi = psi_work;
+        io.tap_psi = psi_stage;
+      }
+      rc = enqueue_forward_io(pl, io, dk_z, b, e, fws, nullptr, st, false);
+      if (rc) return rc;
     }
-    rc = enqueue_forward_io(pl, io, dk_z, b, e, fws, nullptr, st, false);
-    if (rc) return rc;
     // top: second half-step of step e-1, lambda in real space
     ra.ua = staged(e - 1, b);
     ra.ub = staged(e - 1, b) + n2;

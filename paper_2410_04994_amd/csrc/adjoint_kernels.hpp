@@ -417,16 +417,18 @@ __global__ void __launch_bounds__(G * ROWS) row_adj_pass(RowAdjArgs<R> p, RowAdj
   }
   const LdsView<R, 1> a0{&lds[rr][0][0][0]}, a1{&lds[rr][0][1][0]};
   const LdsView<R, 1> b0{&lds[rr][1][0][0]}, b1{&lds[rr][1][1][0]};
+  TwRegs<R, N, G> twr;
+  tw_load(twr, t, p.tw);
   if (p.inv_in) {
-    fft_regs<R, N, G, true, 1>(va, a0, a1, t, p.tw);
-    fft_regs<R, N, G, true, 1>(vb, b0, b1, t, p.tw);
+    fft_pre<R, N, G, true, 1>(va, a0, a1, t, twr);
+    fft_pre<R, N, G, true, 1>(vb, b0, b1, t, twr);
   }
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int m = 0; m < E; ++m) adj_cell<R, TH>(p, q, row + t + G * m, n2, va[m], vb[m], acc);
   if (p.fwd_out) {
-    fft_regs<R, N, G, false, 1>(va, a0, a1, t, p.tw);
-    fft_regs<R, N, G, false, 1>(vb, b0, b1, t, p.tw);
+    fft_pre<R, N, G, false, 1>(va, a0, a1, t, twr);
+    fft_pre<R, N, G, false, 1>(vb, b0, b1, t, twr);
   }
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -459,13 +461,15 @@ __global__ void __launch_bounds__(WideShape<N>::threads) row_adj_pass_wide(RowAd
   const size_t n2 = (size_t)p.ny * N;
   cx<R> v[EF];
   cx<R> la, lb;
+  TwRegs<R, N, G> twr;
+  if (fth) tw_load(twr, t, p.tw);
   if (p.inv_in) {
     if (fth) {
       const cx<R>* src = ff ? p.lb : p.la;
 #pragma unroll
       for (int m = 0; m < EF; ++m) v[m] = src[frow + t + G * m];
     }
-    fft_regs<R, N, G, true, 1>(v, q0, q1, t, p.tw, fth);
+    fft_pre<R, N, G, true, 1>(v, q0, q1, t, twr, fth);
     if (fth) {
 #pragma unroll
       for (int m = 0; m < EF; ++m) cell[ff][fr][pad16(t + G * m)] = v[m];
@@ -488,7 +492,7 @@ __global__ void __launch_bounds__(WideShape<N>::threads) row_adj_pass_wide(RowAd
 #pragma unroll
       for (int m = 0; m < EF; ++m) v[m] = cell[ff][fr][pad16(t + G * m)];
     }
-    fft_regs<R, N, G, false, 1>(v, q0, q1, t, p.tw, fth);
+    fft_pre<R, N, G, false, 1>(v, q0, q1, t, twr, fth);
     if (fth) {
       cx<R>* dst = ff ? p.lb : p.la;
 #pragma unroll

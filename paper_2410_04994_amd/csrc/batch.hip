@@ -4,8 +4,11 @@
 // decreasing nz so that at every boundary the instances still marching form a
 // prefix.  Per boundary s there is one row-pass launch per group (gridDim.y =
 // instances with nz >= s) and per step one column-pass launch per group
-// (gridDim.y = instances with nz > s).  The whole sequence is captured once
-// into a HIP graph and replayed while the arguments stay the same.
+// (gridDim.y = instances with nz > s).  Groups are spread over up to four
+// streams forked from the caller's stream and joined back before the exit
+// powers, so groups run concurrently.  The whole sequence is captured once into
+// a HIP graph (the streams become parallel branches) and replayed while the
+// arguments stay the same.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -133,6 +136,11 @@ bool bcol(int n, int e, int tc, const BatchInst<R>* d, int c, int b, hipStream_t
   }
 }
 
+// Size groups are marched on up to this many concurrent streams, so that the
+// small launches of one group (late z-steps, few active instances) overlap
+// with the work of the others.
+constexpr int kMaxBranches = 4;
+
 struct Group {
   int nx, ny, re, rw, ce, ct, rows;
   int offset;                 // first descriptor of the group
@@ -141,6 +149,7 @@ struct Group {
 
 struct BatchPlanInfo {
   std::vector<Group> groups;
+  std::vector<std::vector<int>> branches;   // group indices per stream
   std::vector<int> order;     // descriptor slot -> caller index
   size_t desc_bytes = 0, phase_off = 0, part_off = 0, total = 0;
   std::vector<size_t> phase_at, part_at;   // per caller index
@@ -152,6 +161,9 @@ struct BatchCache {
   hipGraphExec_t exec = nullptr;
   hipStream_t cap = nullptr;
   void* dev_desc = nullptr;   // inside the workspace; remembered for the key
+  // side streams for the size groups (parallel branches of the captured graph)
+  hipStream_t side[kMaxBranches] = {};
+  hipEvent_t fork = nullptr, join[kMaxBranches] = {};
 };
 
 static int build_info(int n, shg_plan* const* plans, BatchPlanInfo& bi) {
@@ -195,6 +207,23 @@ static int build_info(int n, shg_plan* const* plans, BatchPlanInfo& bi) {
     off += align256((size_t)pl.p.ny * 2 * sizeof(double));
   }
   bi.total = off;
+  // longest-first assignment of the groups to the branches by cell-steps
+  std::vector<std::pair<double, int>> work;
+  for (int gi = 0; gi < (int)bi.groups.size(); ++gi) {
+    double w = 0.0;
+    for (int nz : bi.groups[gi].nzs) w += (double)nz;
+    work.push_back({w * bi.groups[gi].nx * bi.groups[gi].ny, gi});
+  }
+  std::sort(work.begin(), work.end(), [](auto a, auto b) { return a.first > b.first; });
+  const int nb = std::min<int>(kMaxBranches, (int)bi.groups.size());
+  bi.branches.assign(nb, {});
+  std::vector<double> load(nb, 0.0);
+  for (auto& w : work) {
+    const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    bi.branches[b].push_back(w.second);
+    load[b] += w.first;
+  }
+  for (auto& br : bi.branches) std::sort(br.begin(), br.end());
   return SHG_OK;
 }
 
@@ -216,7 +245,8 @@ static int validate_batch(int n, shg_plan* const* plans, void* const* a_f, void*
 template <typename R>
 static int enqueue_batch(int n, shg_plan* const* plans, void* const* a_f, void* const* a_sh,
                          const double* const* dk_z, char* ws, double* powers,
-                         const BatchPlanInfo& bi, hipStream_t st, bool upload) {
+                         const BatchPlanInfo& bi, hipStream_t st, bool upload,
+                         const BatchCache* side) {
   BatchInst<R>* dev = (BatchInst<R>*)ws;
   if (upload) {
     std::vector<BatchInst<R>> host(n);
@@ -266,32 +296,50 @@ static int enqueue_batch(int n, shg_plan* const* plans, void* const* a_f, void* 
     if (e != hipSuccess) return hip_fail(e, "upload of batch descriptors");
   }
   hipLaunchKernelGGL((phase_table_batch<R>), dim3(n), dim3(256), 0, st, (const BatchInst<R>*)dev);
-  int max_nz = 0;
-  for (const Group& g : bi.groups) max_nz = std::max(max_nz, g.nzs[0]);
-  for (int s = 0; s <= max_nz; ++s) {
-    for (const Group& g : bi.groups) {
-      // instances with nz >= s still have boundary s
-      const int cnt = (int)(std::upper_bound(g.nzs.begin(), g.nzs.end(), s, std::greater<int>()) -
-                            g.nzs.begin());
-      if (cnt == 0) continue;
-      if (!brow<R>(g.nx, g.re, g.rw, dev + g.offset, cnt, s, g.ny / g.rows, st))
-        return fail(SHG_EUNSUPPORTED, "batched row schedule not built");
+  hipError_t e = hipSuccess;
+  const int nb = (int)bi.branches.size();
+  const bool fork = nb > 1 && side;
+  if (fork) {
+    e = hipEventRecord(side->fork, st);
+    for (int b = 0; b < nb && e == hipSuccess; ++b) e = hipStreamWaitEvent(side->side[b], side->fork, 0);
+    if (e != hipSuccess) return hip_fail(e, "fork of the batch streams");
+  }
+  for (int b = 0; b < nb; ++b) {
+    hipStream_t bs = fork ? side->side[b] : st;
+    int max_nz = 0;
+    for (int gi : bi.branches[b]) max_nz = std::max(max_nz, bi.groups[gi].nzs[0]);
+    for (int s = 0; s <= max_nz; ++s) {
+      for (int gi : bi.branches[b]) {
+        const Group& g = bi.groups[gi];
+        // instances with nz >= s still have boundary s
+        const int cnt = (int)(std::upper_bound(g.nzs.begin(), g.nzs.end(), s, std::greater<int>()) -
+                              g.nzs.begin());
+        if (cnt == 0) continue;
+        if (!brow<R>(g.nx, g.re, g.rw, dev + g.offset, cnt, s, g.ny / g.rows, bs))
+          return fail(SHG_EUNSUPPORTED, "batched row schedule not built");
+      }
+      if (s == max_nz) break;
+      for (int gi : bi.branches[b]) {
+        const Group& g = bi.groups[gi];
+        // instances with nz > s run step s
+        const int cnt = (int)(std::lower_bound(g.nzs.begin(), g.nzs.end(), s, std::greater<int>()) -
+                              g.nzs.begin());
+        if (cnt == 0) continue;
+        if (!bcol<R>(g.ny, g.ce, g.ct, dev + g.offset, cnt, 2 * (g.nx / g.ct), bs))
+          return fail(SHG_EUNSUPPORTED, "batched column schedule not built");
+      }
     }
-    if (s == max_nz) break;
-    for (const Group& g : bi.groups) {
-      // instances with nz > s run step s
-      const int cnt = (int)(std::lower_bound(g.nzs.begin(), g.nzs.end(), s, std::greater<int>()) -
-                            g.nzs.begin());
-      if (cnt == 0) continue;
-      if (!bcol<R>(g.ny, g.ce, g.ct, dev + g.offset, cnt, 2 * (g.nx / g.ct), st))
-        return fail(SHG_EUNSUPPORTED, "batched column schedule not built");
+    if (fork) {
+      e = hipEventRecord(side->join[b], bs);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, side->join[b], 0);
+      if (e != hipSuccess) return hip_fail(e, "join of the batch streams");
     }
   }
   if (powers) {
     hipLaunchKernelGGL((power_finalize_batch<R>), dim3(n), dim3(256), 0, st,
                        (const BatchInst<R>*)dev);
   }
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return SHG_OK;
 }
@@ -301,6 +349,11 @@ void free_batch(Plan& pl) {
   if (!bc) return;
   if (bc->exec) (void)hipGraphExecDestroy(bc->exec);
   if (bc->cap) (void)hipStreamDestroy(bc->cap);
+  for (int b = 0; b < kMaxBranches; ++b) {
+    if (bc->side[b]) (void)hipStreamDestroy(bc->side[b]);
+    if (bc->join[b]) (void)hipEventDestroy(bc->join[b]);
+  }
+  if (bc->fork) (void)hipEventDestroy(bc->fork);
   delete bc;
   pl.batch = nullptr;
 }
@@ -350,10 +403,29 @@ static int propagate_batch(int n, shg_plan* const* plans, void* const* a_f, void
   hipError_t e = hipStreamIsCapturing(st, &cs);
   if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
   const bool same = bc->exec && bc->key == key;
+  if (bi.branches.size() > 1 && !bc->fork) {
+    for (int b = 0; b < kMaxBranches && e == hipSuccess; ++b) {
+      e = hipStreamCreateWithFlags(&bc->side[b], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&bc->join[b], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&bc->fork, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      for (int b = 0; b < kMaxBranches; ++b) {
+        if (bc->side[b]) (void)hipStreamDestroy(bc->side[b]);
+        if (bc->join[b]) (void)hipEventDestroy(bc->join[b]);
+        bc->side[b] = nullptr;
+        bc->join[b] = nullptr;
+      }
+      if (bc->fork) (void)hipEventDestroy(bc->fork);
+      bc->fork = nullptr;
+      return hip_fail(e, "creating the batch side streams");
+    }
+  }
+  const BatchCache* side = bc->fork ? bc : nullptr;
   auto enqueue = [&](hipStream_t s, bool upload) {
     return p0.dtype == SHG_C64
-               ? enqueue_batch<float>(n, plans, a_f, a_sh, dk_z, (char*)ws, powers, bi, s, upload)
-               : enqueue_batch<double>(n, plans, a_f, a_sh, dk_z, (char*)ws, powers, bi, s, upload);
+               ? enqueue_batch<float>(n, plans, a_f, a_sh, dk_z, (char*)ws, powers, bi, s, upload, side)
+               : enqueue_batch<double>(n, plans, a_f, a_sh, dk_z, (char*)ws, powers, bi, s, upload, side);
   };
   if (cs != hipStreamCaptureStatusNone) {
     // the caller records this call into its own graph: the descriptors must

@@ -286,6 +286,103 @@ __device__ __forceinline__ void stockham(cx<R> (&v)[N / G], LdsView<R, STRIDE> i
   }
 }
 
+// ---------------------------------------------------------------- twiddle prefetch
+// The twiddles a thread needs depend only on its index, so they are loaded
+// into registers once, before the first barrier, and reused for the forward
+// and the inverse transform of a pass (conjugated).  Otherwise each Stockham
+// pass would issue its twiddle loads after a barrier and wait on them.
+template <int N, int G, int NS, int REM>
+struct TwCount {
+  static constexpr int E = N / G;
+  static constexpr int RP = pick_radix<E, REM>::value;
+  static constexpr int NB = E / RP;
+  static constexpr int here = NS > 1 ? NB * (RP - 1) : 0;
+  static constexpr int value = here + TwCount<N, G, NS * RP, REM / RP>::value;
+};
+template <int N, int G, int NS>
+struct TwCount<N, G, NS, 1> {
+  static constexpr int value = 0;
+};
+
+template <typename R, int N, int G>
+struct TwRegs {
+  static constexpr int count = TwCount<N, G, 1, N>::value;
+  Tw<R> w[count > 0 ? count : 1];
+};
+
+template <typename R, int N, int G, int NS, int REM>
+__device__ __forceinline__ void tw_gather(Tw<R>* out, int t, const Tw<R>* __restrict__ tw) {
+  if constexpr (REM > 1) {
+    constexpr int E = N / G;
+    constexpr int RP = pick_radix<E, REM>::value;
+    constexpr int NB = E / RP;
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int jm = (t + G * u) % NS;
+#pragma unroll
+        for (int r = 1; r < RP; ++r) out[u * (RP - 1) + (r - 1)] = tw[jm * r * (N / (NS * RP))];
+      }
+      tw_gather<R, N, G, NS * RP, REM / RP>(out + NB * (RP - 1), t, tw);
+    } else {
+      tw_gather<R, N, G, NS * RP, REM / RP>(out, t, tw);
+    }
+  }
+}
+
+template <typename R, int N, int G>
+__device__ __forceinline__ void tw_load(TwRegs<R, N, G>& T, int t, const Tw<R>* __restrict__ tw) {
+  tw_gather<R, N, G, 1, N>(T.w, t, tw);
+}
+
+// Stockham pass reading its twiddles from the prefetched registers.
+template <typename R, int N, int G, bool INV, int NS, int REM, bool FIRST, int STRIDE>
+__device__ __forceinline__ void stockham_pre(cx<R> (&v)[N / G], LdsView<R, STRIDE> in,
+                                             LdsView<R, STRIDE> out, int t, const Tw<R>* twr,
+                                             bool active) {
+  constexpr int E = N / G;
+  constexpr int RP = pick_radix<E, REM>::value;
+  constexpr int NB = E / RP;
+  constexpr bool LAST = (REM == RP);
+#pragma unroll
+  for (int u = 0; u < NB && active; ++u) {
+    const int j = t + G * u;
+    cx<R> x[RP];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) x[r] = FIRST ? v[u + r * NB] : in[j + r * (N / RP)];
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < RP; ++r) {
+        const Tw<R> w = twr[u * (RP - 1) + (r - 1)];
+        x[r] = cmul_split<K16<R>::split>(x[r], w.c, INV ? -w.s : w.s, w.cl, INV ? -w.sl : w.sl);
+      }
+    }
+    dft<RP, INV>(x);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int r = 0; r < RP; ++r) v[u + r * NB] = x[r];
+    } else {
+      const int d = (j / NS) * NS * RP + (j % NS);
+#pragma unroll
+      for (int r = 0; r < RP; ++r) out[d + r * NS] = x[r];
+    }
+  }
+  if constexpr (!LAST) {
+    __syncthreads();
+    constexpr int used = NS > 1 ? NB * (RP - 1) : 0;
+    stockham_pre<R, N, G, INV, NS * RP, REM / RP, false, STRIDE>(v, out, in, t, twr + used,
+                                                                active);
+  }
+}
+
+template <typename R, int N, int G, bool INV, int STRIDE>
+__device__ __forceinline__ void fft_pre(cx<R> (&v)[N / G], LdsView<R, STRIDE> b0,
+                                        LdsView<R, STRIDE> b1, int t, const TwRegs<R, N, G>& T,
+                                        bool active = true) {
+  if constexpr (pick_radix<N / G, N>::value < N) __syncthreads();
+  stockham_pre<R, N, G, INV, 1, N, true, STRIDE>(v, b0, b1, t, T.w, active);
+}
+
 // Whole transform of the registers v.  All threads of the block must call it
 // (it contains block barriers); one leading barrier protects LDS reuse.
 // Threads with active = false only take part in the barriers.

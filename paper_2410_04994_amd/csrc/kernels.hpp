@@ -213,9 +213,11 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
   }
   const LdsView<R, 1> a0{&lds[rr][0][0][0]}, a1{&lds[rr][0][1][0]};
   const LdsView<R, 1> b0{&lds[rr][1][0][0]}, b1{&lds[rr][1][1][0]};
+  TwRegs<R, N, G> twr;
+  tw_load(twr, t, p.tw);
   if (p.inv_in) {
-    fft_regs<R, N, G, true, 1>(va, a0, a1, t, p.tw);
-    fft_regs<R, N, G, true, 1>(vb, b0, b1, t, p.tw);
+    fft_pre<R, N, G, true, 1>(va, a0, a1, t, twr);
+    fft_pre<R, N, G, true, 1>(vb, b0, b1, t, twr);
   }
   const bool und = p.undepleted != 0;
   if (p.tap_a) {
@@ -263,8 +265,8 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
     }
   }
   if (p.fwd_out) {
-    fft_regs<R, N, G, false, 1>(va, a0, a1, t, p.tw);
-    fft_regs<R, N, G, false, 1>(vb, b0, b1, t, p.tw);
+    fft_pre<R, N, G, false, 1>(va, a0, a1, t, twr);
+    fft_pre<R, N, G, false, 1>(vb, b0, b1, t, twr);
   }
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -340,13 +342,15 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
   const size_t idx = (size_t)(blk * ROWS + cr) * N + cxi;
   cx<R> v[EF];
   cx<R> a, b;
+  TwRegs<R, N, G> twr;
+  if (fth) tw_load(twr, t, p.tw);
   if (p.inv_in) {
     if (fth) {
       const cx<R>* src = ff ? p.bin : p.ain;
 #pragma unroll
       for (int m = 0; m < EF; ++m) v[m] = src[frow + t + G * m];
     }
-    fft_regs<R, N, G, true, 1>(v, q0, q1, t, p.tw, fth);
+    fft_pre<R, N, G, true, 1>(v, q0, q1, t, twr, fth);
     if (fth) {
 #pragma unroll
       for (int m = 0; m < EF; ++m) cell[ff][fr][pad16(t + G * m)] = v[m];
@@ -401,7 +405,7 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
 #pragma unroll
       for (int m = 0; m < EF; ++m) v[m] = cell[ff][fr][pad16(t + G * m)];
     }
-    fft_regs<R, N, G, false, 1>(v, q0, q1, t, p.tw, fth);
+    fft_pre<R, N, G, false, 1>(v, q0, q1, t, twr, fth);
     if (fth) {
       cx<R>* dst = ff ? p.bout : p.aout;
 #pragma unroll
@@ -462,7 +466,9 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& p) {
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = col[(size_t)(t + G * m) * p.nx];
   const LdsView<R, TC> b0{&lds[0][c]}, b1{&lds[1][c]};
-  fft_regs<R, N, G, false, TC>(v, b0, b1, t, p.tw);
+  TwRegs<R, N, G> twr;
+  tw_load(twr, t, p.tw);
+  fft_pre<R, N, G, false, TC>(v, b0, b1, t, twr);
   // diffraction + linear loss (Eq. A.4), product formed in FP64
   const double* __restrict__ mxp = p.mx[field];
   const double* __restrict__ myp = p.my[field];
@@ -477,7 +483,7 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& p) {
     const double vr = (double)v[m].re, vi = (double)v[m].im;
     v[m] = {(R)(vr * mr - vi * mi), (R)(vr * mi + vi * mr)};
   }
-  fft_regs<R, N, G, true, TC>(v, b0, b1, t, p.tw);
+  fft_pre<R, N, G, true, TC>(v, b0, b1, t, twr);
 #pragma unroll
   for (int m = 0; m < E; ++m) col[(size_t)(t + G * m) * p.nx] = v[m];
 }

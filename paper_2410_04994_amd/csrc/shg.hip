@@ -236,8 +236,8 @@ struct SchedRow {
 };
 static const SchedRow kSingle[] = {{16, 1, 256, 4, 16}, {32, 1, 256, 4, 8}, {64, 1, 256, 4, 4},
                                    {128, 1, 256, 4, 2}, {256, 1, 256, 4, 2}, {512, 1, 512, 8, 4}};
-static const SchedRow kBatch[] = {{16, 4, 64, 4, 16}, {32, 4, 64, 4, 16}, {64, 4, 64, 8, 8},
-                                  {128, 8, 64, 16, 8}, {256, 8, 64, 16, 4}, {512, 8, 64, 16, 4}};
+static const SchedRow kBatch[] = {{16, 4, 64, 4, 16}, {32, 4, 64, 4, 16}, {64, 4, 64, 4, 8},
+                                  {128, 4, 64, 8, 4}, {256, 4, 64, 8, 8}, {512, 4, 64, 8, 4}};
 
 static bool apply_row(Plan& pl, int re, int rw, int* rows) { return row_supported(pl, re, rw, rows); }
 
@@ -365,6 +365,27 @@ int validate_params(const shg_params* p) {
 static constexpr double kEps0 = 8.8541878128e-12;
 static constexpr double kC = 299792458.0;
 
+// Default adjoint checkpoint interval K.  The adjoint keeps ceil(nz/K) + 1
+// checkpoints and stages K steps (both fields plus the temperature phase Psi,
+// 5 reals per cell); the last segment is staged by the forward sweep itself, so
+// only the first nz - K steps are recomputed.  K = nz (nothing recomputed) when
+// that fits in kAdjointStateBudget, else the largest K whose checkpoints and
+// staging fit, but at least ceil(sqrt(nz)).
+static constexpr size_t kAdjointStateBudget = size_t(4) << 30;
+
+static int auto_checkpoint(int nz, size_t cells, int real_bytes) {
+  const size_t per_step = cells * 5 * (size_t)real_bytes;
+  const size_t slots = std::max<size_t>(1, kAdjointStateBudget / per_step);
+  if ((size_t)nz + 2 <= slots) return nz;
+  int k_min = 1;
+  while ((size_t)k_min * k_min < (size_t)nz) ++k_min;
+  for (int k = nz; k > k_min; --k) {
+    const size_t segs = ((size_t)nz + k - 1) / k;
+    if ((size_t)k + segs + 1 <= slots) return k;
+  }
+  return k_min;
+}
+
 int build_plan(Plan& pl) {
   const shg_params& p = pl.p;
   const double lam_f = p.lambda_f, lam_sh = lam_f / 2.0;
@@ -381,8 +402,9 @@ int build_plan(Plan& pl) {
   pl.lens_sh = 2.0 * M_PI * p.dn_dT / lam_sh;
   pl.pscale_f = kEps0 * kC * p.n_f / 2.0 * pl.dx * pl.dy;
   pl.pscale_sh = kEps0 * kC * p.n_sh / 2.0 * pl.dx * pl.dy;
-  pl.ckpt = p.checkpoint_every > 0 ? p.checkpoint_every : 32;
   pl.real_bytes = pl.dtype == SHG_C64 ? 4 : 8;
+  pl.ckpt = p.checkpoint_every > 0 ? std::min(p.checkpoint_every, p.nz)
+                                   : auto_checkpoint(p.nz, (size_t)p.nx * p.ny, pl.real_bytes);
   int rc;
   if (pl.dtype == SHG_C64) {
     auto tx = twiddles<float>(p.nx), ty = twiddles<float>(p.ny);
@@ -785,10 +807,11 @@ int shg_plan_describe(const shg_plan* plan, char* buf, size_t len) {
   const Plan* pl = reinterpret_cast<const Plan*>(plan);
   if (buf && len) {
     snprintf(buf, len,
-             "dtype=%s nx=%d ny=%d nz=%d row(e=%d wg=%d rows=%d) adj(e=%d wg=%d) col(e=%d tc=%d) "
-             "batch(row e=%d wg=%d col e=%d tc=%d) graph=%d",
+             "dtype=%s nx=%d ny=%d nz=%d row(e=%d wg=%d rows=%d) adj(e=%d wg=%d K=%d) "
+             "col(e=%d tc=%d) batch(row e=%d wg=%d col e=%d tc=%d) graph=%d",
              pl->dtype == SHG_C64 ? "c64" : "c128", pl->p.nx, pl->p.ny, pl->p.nz, pl->row_e,
-             pl->row_wg, pl->row_rows, pl->adj_e, pl->adj_wg, pl->col_e, pl->col_tc, pl->b_row_e,
+             pl->row_wg, pl->row_rows, pl->adj_e, pl->adj_wg, pl->ckpt, pl->col_e, pl->col_tc,
+             pl->b_row_e,
              pl->b_row_wg, pl->b_col_e, pl->b_col_tc,
              (pl->p.flags & SHG_NO_GRAPH) ? 0 : 1);
   }

@@ -83,7 +83,7 @@ def test_checkpoint_interval_does_not_change_the_result():
     is compared to 1e-6."""
     wl, a0, b0, gf, gs, w, dk = small_case(n=32, nz=13)
     base = gpu_adjoint(wl, "c64", a0, b0, gf, gs, w, dk, ckpt=1)
-    for k in (2, 5, 13, 64):
+    for k in (2, 5, 13, 64, 0):     # 0: the library's default (all 13 steps staged)
         got = gpu_adjoint(wl, "c64", a0, b0, gf, gs, w, dk, ckpt=k)
         for key in ("g_f", "g_sh", "a_f", "a_sh", "powers"):
             assert np.array_equal(got[key], base[key]), (k, key)
