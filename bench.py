@@ -15,7 +15,7 @@ Printed JSON line:
   cpu_baseline the FP64 oracle on a bounded sample of the same workload
   extras       batched and forward+adjoint throughput when those paths run
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 2]
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2]
 """
 from __future__ import annotations
 
@@ -79,7 +79,7 @@ def cpu_baseline(wl, sample_steps: int):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sample-steps", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -161,7 +161,8 @@ def main(argv=None):
                 "traffic": traffic, "kernel": dom, "avg_launch_us": round(avg_ms * 1e3, 3),
                 "algorithmic_bytes_per_launch": int(launch_bytes),
                 "row_pass_avg_us": round(row_avg * 1e3, 3), "col_pass_avg_us": round(col_avg * 1e3, 3),
-                "whole_march_frac_at_64B": round(value * 64.0 / (HBM_PEAK_GBS * 1e9), 4)}
+                "whole_march_frac_at_64B": round(value * 64.0 / (HBM_PEAK_GBS * 1e9), 4),
+                "whole_march_frac_at_32B": round(value * 32.0 / (HBM_PEAK_GBS * 1e9), 4)}
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "cell-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
