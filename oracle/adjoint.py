@@ -156,8 +156,9 @@ def adjoint(p: dict, a_f0: np.ndarray, a_sh0: np.ndarray, g_f_out: np.ndarray,
     nz = p["nz"]
     und = bool(p.get("undepleted", False))
     fwd = ssfm.propagate(p, a_f0, a_sh0, dk_z, temp, return_states=True)
-    m_f = ssfm.propagator(p, c.k_f, p["alpha_f"], dz)
-    m_sh = ssfm.propagator(p, c.k_sh, p["alpha_sh"], dz)
+    rho_f, rho_sh = ssfm.walkoff_angles(p)
+    m_f = ssfm.propagator(p, c.k_f, p["alpha_f"], dz, rho_f)
+    m_sh = ssfm.propagator(p, c.k_sh, p["alpha_sh"], dz, rho_sh)
 
     cf = ssfm.EPS0 * ssfm.C_LIGHT * p["n_f"] / 2 * c.dx * c.dy
     cs = ssfm.EPS0 * ssfm.C_LIGHT * p["n_sh"] / 2 * c.dx * c.dy

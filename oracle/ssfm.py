@@ -26,10 +26,16 @@ the design notes and pinned by a test in tests/test_oracle_pins.py):
     thermal-lens term -i (2 pi/lambda_j)(dn/dT)(T - T_ref) A_j, with T sampled
     at the step mid-plane.
   * undepleted pump (Sec. 5.1): the nonlinear part of dA_F/dz is zero.
+  * spatial walk-off (optional; Sec. 4, the propagator set-up of the package
+    description): dA_j/dz gains -tan(rho_j) dA_j/dx, a linear term that moves the
+    beam of wave j towards +x by tan(rho_j) per unit length.  It is part of L,
+    i.e. a factor exp(-2 i pi qx tan(rho_j) dz) of the propagator.  rho_j comes
+    from params "walkoff_f" / "walkoff_sh" (rad, default 0).
 
 Discrete scheme, one z-step s on [z_s, z_s + dz] (Eq. 14, order N/2 - L - N/2):
   y <- RK4 over [z_s, z_s + dz/2] of the pointwise nonlinear system
-  A_j <- IFFT2( M_j * FFT2(A_j) ),  M_j = exp[(2 i pi^2 (qx^2 + qy^2)/k_j - alpha_j/2) dz]
+  A_j <- IFFT2( M_j * FFT2(A_j) ),
+         M_j = exp[(2 i pi^2 (qx^2 + qy^2)/k_j - alpha_j/2 - 2 i pi qx tan(rho_j)) dz]
   y <- RK4 over [z_s + dz/2, z_s + dz]
 Grid: x_m = (m - Nx/2) dx, dx = Lx/Nx (periodic window); q = fftfreq(N, dx)
 in cycles per metre, which is the transform pair of Eq. A.2.
@@ -85,13 +91,20 @@ def coordinates(p: dict):
     return x, y
 
 
-def propagator(p: dict, k: float, alpha: float, dz: float) -> np.ndarray:
+def propagator(p: dict, k: float, alpha: float, dz: float, walkoff: float = 0.0) -> np.ndarray:
     """Fourier-space propagator of the linear operator over dz (Eqs. A.3-A.5 with
-    the linear loss of Eq. 11): exp[(2 i pi^2 (qx^2+qy^2)/k - alpha/2) dz]."""
+    the linear loss of Eq. 11 and the walk-off term):
+    exp[(2 i pi^2 (qx^2+qy^2)/k - alpha/2 - 2 i pi qx tan(walkoff)) dz]."""
     qx = np.fft.fftfreq(p["nx"], p["lx"] / p["nx"])
     qy = np.fft.fftfreq(p["ny"], p["ly"] / p["ny"])
     q2 = qy[:, None] ** 2 + qx[None, :] ** 2
-    return np.exp((2j * math.pi ** 2 * q2 / k - alpha / 2.0) * dz)
+    drift = 2j * math.pi * math.tan(walkoff) * qx[None, :]
+    return np.exp((2j * math.pi ** 2 * q2 / k - alpha / 2.0 - drift) * dz)
+
+
+def walkoff_angles(p: dict):
+    """(rho_F, rho_SH) in rad; zero when the parameters do not set them."""
+    return p.get("walkoff_f", 0.0), p.get("walkoff_sh", 0.0)
 
 
 def linear_step(a: np.ndarray, m: np.ndarray) -> np.ndarray:
@@ -162,8 +175,9 @@ def propagate(p: dict, a_f: np.ndarray, a_sh: np.ndarray, dk_z: Optional[np.ndar
     c = coefficients(p)
     dz = c.dz
     undepleted = bool(p.get("undepleted", False))
-    m_f = propagator(p, c.k_f, p["alpha_f"], dz)
-    m_sh = propagator(p, c.k_sh, p["alpha_sh"], dz)
+    rho_f, rho_sh = walkoff_angles(p)
+    m_f = propagator(p, c.k_f, p["alpha_f"], dz, rho_f)
+    m_sh = propagator(p, c.k_sh, p["alpha_sh"], dz, rho_sh)
     a = np.array(a_f, dtype=np.complex128)
     b = np.array(a_sh, dtype=np.complex128)
 

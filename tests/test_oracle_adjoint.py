@@ -36,9 +36,10 @@ def loss(p, a, b, g_f, g_sh, w, dk_z=None, temp=None):
             + w[0] * out["p_f"] + w[1] * out["p_sh"])
 
 
-@pytest.mark.parametrize("with_temp,undepleted", [(False, False), (True, False), (True, True)])
-def test_adjoint_matches_central_differences(with_temp, undepleted):
-    p = params(undepleted=undepleted)
+@pytest.mark.parametrize("with_temp,undepleted,walkoff", [(False, False, 0.0), (True, False, 0.0),
+                                                          (True, True, 0.0), (False, False, 0.02)])
+def test_adjoint_matches_central_differences(with_temp, undepleted, walkoff):
+    p = params(undepleted=undepleted, walkoff_sh=walkoff, walkoff_f=-0.5 * walkoff)
     r = rng(21)
     shape = (p["ny"], p["nx"])
     a = crand(r, shape, 5e7)

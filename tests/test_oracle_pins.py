@@ -406,3 +406,59 @@ def test_resume_from_midpoint():
     half = ssfm.propagate(p, a, b, s_end=9)
     rest = ssfm.propagate(p, half["a_f"], half["a_sh"], s_begin=9)
     assert rel(rest["a_sh"], full["a_sh"]) < 1e-14
+
+
+# --------------------------------------------------------------------- walk-off
+def test_walkoff_on_both_waves_is_an_exact_translation():
+    """Spatial walk-off (the tan(rho) dA/dx term of the propagators, Sec. 4).
+    With the same angle on both waves the coupled march is the rho = 0 march
+    translated by tan(rho) z, since every other term is pointwise or
+    translation invariant.  With tan(rho) dz = dx the translation is one sample
+    per step, so the result must equal np.roll of the rho = 0 result, on a
+    depleted march with mismatch, loss, TPA and a random input phase."""
+    lcr, xi, n, nz = 10e-3, 2.0, 64, 24
+    w0 = waist(lcr, xi)
+    p0 = base_params(n=n, nz=nz, lcr=lcr, width=10 * w0 * math.sqrt(1 + xi * xi),
+                     dk0=-150.0, alpha_f=0.5, alpha_sh=1.0, beta_f=1e-11, beta_sh=1e-11)
+    rng = np.random.Generator(np.random.PCG64(21))
+    a0 = beams.input_pump(p0, 2e3, w0, lcr / 2, 0.2 * rng.normal(size=(n, n)))
+    b0 = 1e-3 * np.abs(a0).max() * (rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n)))
+    ref = ssfm.propagate(p0, a0, b0)
+    assert np.abs(ref["a_sh"]).max() > 1e-2 * np.abs(ref["a_f"]).max()   # real coupling
+    dx, dz = p0["lx"] / n, lcr / nz
+    rho = math.atan(dx / dz)
+    out = ssfm.propagate(dict(p0, walkoff_f=rho, walkoff_sh=rho), a0, b0)
+    for key in ("a_f", "a_sh"):
+        assert rel(out[key], np.roll(ref[key], nz, axis=1)) < 1e-12, key
+        # the opposite sign or a missing wave is far off
+        assert rel(out[key], np.roll(ref[key], -nz, axis=1)) > 1e-2
+    only_sh = ssfm.propagate(dict(p0, walkoff_sh=rho), a0, b0)
+    assert rel(only_sh["a_sh"], out["a_sh"]) > 1e-2
+
+
+def test_walkoff_moves_the_centroid_by_tan_rho_z():
+    """One wave with walk-off, linear propagation (d = 0): its intensity centroid
+    moves by tan(rho) L along +x (a non-integer number of samples); the other
+    wave and the y centroid stay put; power is unchanged."""
+    lcr, xi, n, nz = 10e-3, 1.0, 128, 10
+    w0 = waist(lcr, xi)
+    width = 16 * w0 * math.sqrt(1 + xi * xi)
+    rho = math.atan(7.37 * (width / n) / lcr)          # 7.37 samples over the crystal
+    p = base_params(n=n, nz=nz, lcr=lcr, width=width, d_eff=0.0, walkoff_sh=rho)
+    a0 = beams.input_pump(p, 1.0, w0, lcr / 2)
+    out = ssfm.propagate(p, a0, a0.copy())
+    x, y = ssfm.coordinates(p)
+
+    def centroid(f):
+        i = np.abs(f) ** 2
+        return float(np.sum(i * x[None, :]) / np.sum(i)), float(np.sum(i * y[:, None]) / np.sum(i))
+
+    cx0, cy0 = centroid(a0)
+    cxs, cys = centroid(out["a_sh"])
+    cxf, cyf = centroid(out["a_f"])
+    shift = math.tan(rho) * lcr
+    assert 0.2 < (shift / (p["lx"] / n)) % 1.0 < 0.8    # not a whole number of samples
+    assert abs((cxs - cx0) / shift - 1) < 1e-9
+    assert abs(cys - cy0) < 1e-12 * p["ly"] and abs(cxf - cx0) < 1e-12 * p["lx"]
+    c = ssfm.coefficients(p)
+    assert abs(ssfm.power(out["a_sh"], 1.0, c.dx, c.dy) / ssfm.power(a0, 1.0, c.dx, c.dy) - 1) < 1e-12

@@ -61,6 +61,8 @@ class Workload:
     ddk_dT: float = 0.0
     dn_dT: float = 0.0
     t_ref: float = 0.0
+    walkoff_f: float = 0.0         # spatial walk-off angle of the fundamental [rad]
+    walkoff_sh: float = 0.0        # spatial walk-off angle of the SH [rad]
     undepleted: bool = False
     phase_noise_std: float = 0.0   # std of the i.i.d. input phase mask [rad]
     seed: int = 0
@@ -72,7 +74,7 @@ class Workload:
         """Plain parameter dict understood by both the oracle and the binding."""
         keys = ("nx", "ny", "nz", "lx", "ly", "lcr", "lambda_f", "n_f", "n_sh", "d_eff",
                 "alpha_f", "alpha_sh", "beta_f", "beta_sh", "dk0", "ddk_dT", "dn_dT",
-                "t_ref", "undepleted")
+                "t_ref", "walkoff_f", "walkoff_sh", "undepleted")
         return {k: getattr(self, k) for k in keys}
 
     @property
