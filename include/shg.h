@@ -17,7 +17,11 @@
  *   - with a temperature field, dk = dk_s + ddk_dT (T - t_ref) per cell and a
  *     thermal-lens term -i (2 pi / lambda_j) dn_dT (T - t_ref) A_j, with T given
  *     at each step's mid-plane;
- *   - SHG_UNDEPLETED zeroes the whole nonlinear part of dA_F/dz (Sec. 5.1).
+ *   - SHG_UNDEPLETED zeroes the whole nonlinear part of dA_F/dz (Sec. 5.1);
+ *   - spatial walk-off (the tan(rho) dA/dx term of the package's propagators,
+ *     Sec. 4): dA_j/dz gains -tan(rho_j) dA_j/dx, which moves wave j towards +x
+ *     by tan(rho_j) per metre; it is linear and applied exactly in L as
+ *     exp(-2 i pi q_x tan(rho_j) dz).
  *
  * Conventions.
  *   - SI units throughout: m, W, rad/m, 1/m (intensity absorption), m/W, K.
@@ -80,6 +84,8 @@ typedef struct {
   uint32_t flags;         /* SHG_UNDEPLETED | SHG_NO_GRAPH                      */
   int32_t checkpoint_every; /* adjoint checkpoint interval K (0 -> automatic:  */
                             /* K = nz when nz staged steps fit in 4 GiB)       */
+  double walkoff_f, walkoff_sh; /* spatial walk-off angles rho_F, rho_SH [rad], */
+                            /* |rho| < pi/2; 0 for quasi-phase matching        */
 } shg_params;
 
 /* Create a plan: validates the parameters, builds the FP64 propagator and
@@ -88,7 +94,8 @@ typedef struct {
  * device tables on the current HIP device.
  * Errors: SHG_EINVAL (NULL pointer, nx/ny not a power of two in [16, 512],
  * nz < 1, non-positive or non-finite lengths/indices/wavelength, negative
- * absorption), SHG_ENOMEM, SHG_EDEVICE.  *out is NULL on error. */
+ * absorption, |walk-off| >= pi/2), SHG_ENOMEM, SHG_EDEVICE.  *out is NULL on
+ * error. */
 int shg_plan_create(shg_plan **out, const shg_params *p, shg_dtype dtype);
 
 /* Release the plan and its device tables.  NULL is accepted (returns SHG_OK).

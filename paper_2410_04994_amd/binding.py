@@ -36,7 +36,8 @@ class ShgParams(ctypes.Structure):
                 ("alpha_sh", ctypes.c_double), ("beta_f", ctypes.c_double),
                 ("beta_sh", ctypes.c_double), ("dk0", ctypes.c_double), ("ddk_dT", ctypes.c_double),
                 ("dn_dT", ctypes.c_double), ("t_ref", ctypes.c_double), ("flags", ctypes.c_uint32),
-                ("checkpoint_every", ctypes.c_int32)]
+                ("checkpoint_every", ctypes.c_int32), ("walkoff_f", ctypes.c_double),
+                ("walkoff_sh", ctypes.c_double)]
 
 
 _VP = ctypes.c_void_p
@@ -110,7 +111,8 @@ def _stream(stream=None):
 
 
 PARAM_KEYS = ("nx", "ny", "nz", "lx", "ly", "lcr", "lambda_f", "n_f", "n_sh", "d_eff", "alpha_f",
-              "alpha_sh", "beta_f", "beta_sh", "dk0", "ddk_dT", "dn_dT", "t_ref")
+              "alpha_sh", "beta_f", "beta_sh", "dk0", "ddk_dT", "dn_dT", "t_ref", "walkoff_f",
+              "walkoff_sh")
 
 
 def make_params(params: dict, flags: int = 0, checkpoint_every: int = 0) -> ShgParams:

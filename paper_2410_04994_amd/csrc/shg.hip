@@ -315,11 +315,13 @@ static double fftfreq(int i, int n, double d) {
 }
 
 // exp(2 i pi^2 q^2 dz / k) for q = fftfreq(n, d); optional extra real factor.
-static std::vector<double> prop_factor(int n, double d, double dz, double k, double extra) {
+static std::vector<double> prop_factor(int n, double d, double dz, double k, double extra,
+                                       double tan_walkoff = 0.0) {
   std::vector<double> out(2 * n);
   for (int i = 0; i < n; ++i) {
     const double q = fftfreq(i, n, d);
-    const double th = 2.0 * M_PI * M_PI * q * q * dz / k;
+    // diffraction, plus the walk-off translation by tan(rho) dz (x axis only)
+    const double th = 2.0 * M_PI * M_PI * q * q * dz / k - 2.0 * M_PI * q * tan_walkoff * dz;
     out[2 * i] = extra * std::cos(th);
     out[2 * i + 1] = extra * std::sin(th);
   }
@@ -357,6 +359,8 @@ int validate_params(const shg_params* p) {
       !std::isfinite(p->t_ref))
     return fail(SHG_EINVAL, "dk0, ddk_dT, dn_dT, t_ref must be finite");
   if (p->checkpoint_every < 0) return fail(SHG_EINVAL, "checkpoint_every must be >= 0");
+  if (!(std::fabs(p->walkoff_f) < M_PI / 2) || !(std::fabs(p->walkoff_sh) < M_PI / 2))
+    return fail(SHG_EINVAL, "walk-off angles must be finite with |rho| < pi/2");
   if (p->flags & ~(uint32_t)(SHG_UNDEPLETED | SHG_NO_GRAPH))
     return fail(SHG_EINVAL, "unknown flag bits 0x%x", p->flags);
   return SHG_OK;
@@ -418,8 +422,9 @@ int build_plan(Plan& pl) {
   const double norm = 1.0 / ((double)p.nx * (double)p.ny);
   const double ks[2] = {pl.k_f, pl.k_sh};
   const double al[2] = {p.alpha_f, p.alpha_sh};
+  const double rho[2] = {p.walkoff_f, p.walkoff_sh};
   for (int w = 0; w < 2; ++w) {
-    auto mx = prop_factor(p.nx, pl.dx, pl.dz, ks[w], 1.0);
+    auto mx = prop_factor(p.nx, pl.dx, pl.dz, ks[w], 1.0, std::tan(rho[w]));
     auto my = prop_factor(p.ny, pl.dy, pl.dz, ks[w], std::exp(-al[w] * pl.dz / 2.0) * norm);
     if ((rc = upload((void**)&pl.mx[w], mx.data(), mx.size() * sizeof(double)))) return rc;
     if ((rc = upload((void**)&pl.my[w], my.data(), my.size() * sizeof(double)))) return rc;

@@ -78,7 +78,8 @@ def create(lib, p, dtype=0, flags=0):
     (dict(nz=0), "nz"), (dict(lx=-1.0), "lx"), (dict(lcr=float("nan")), "lcr"),
     (dict(n_sh=0.0), "n_sh"), (dict(alpha_f=-1.0), "absorption"),
     (dict(beta_sh=float("inf")), "absorption"), (dict(dk0=float("nan")), "dk0"),
-    (dict(d_eff=float("inf")), "d_eff"),
+    (dict(d_eff=float("inf")), "d_eff"), (dict(walkoff_sh=1.6), "walk-off"),
+    (dict(walkoff_f=float("nan")), "walk-off"),
 ])
 def test_invalid_params_rejected_before_device(lib, bad, needle):
     rc, h, msg = create(lib, good_params(**bad))

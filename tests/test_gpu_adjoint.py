@@ -65,6 +65,16 @@ def test_complex128_adjoint_matches_oracle(undepleted):
     assert rel(got["a_sh"], ref["forward"]["a_sh"]) < 1e-12
 
 
+def test_walkoff_adjoint_matches_oracle():
+    """The adjoint of the walk-off factor is its conjugate, like the rest of L."""
+    wl, a0, b0, gf, gs, w, dk = small_case()
+    wl = wl.with_(walkoff_sh=0.05 * wl.lx / wl.lcr, walkoff_f=0.02 * wl.lx / wl.lcr)
+    ref = oracle_adjoint(wl, a0, b0, gf, gs, w, dk)
+    got = gpu_adjoint(wl, "c128", a0, b0, gf, gs, w, dk, ckpt=6)
+    for key in ("g_f", "g_sh", "g_dk"):
+        assert rel(got[key], ref[key]) < 1e-10, key
+
+
 def test_complex64_adjoint_matches_oracle():
     wl, a0, b0, gf, gs, w, dk = small_case(n=64, nz=40)
     ref = oracle_adjoint(wl, a0, b0, gf, gs, w, dk)

@@ -231,3 +231,17 @@ def test_temperature_field_full_grid():
     gpu = run_gpu(plan, a0, b0, temp=temp)
     ref = run_oracle(wl, a0, b0, temp=temp.astype(np.float64))
     compare(wl, gpu, ref, "c64", "thermal 512 " + plan.describe())
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_spatial_walkoff(dtype):
+    """Walk-off on the SH (type-I birefringent matching) and a smaller one on
+    the fundamental: the tan(rho) dA/dx term rides in the x propagator factor."""
+    base = workloads.c2_plain_c64()
+    wl = base.with_(nx=64, ny=64, nz=120, walkoff_sh=0.1 * base.lx / base.lcr,
+                    walkoff_f=-0.03 * base.lx / base.lcr)
+    parity(wl, dtype)
+    a0, b0 = inputs(wl, dtype)
+    plain = run_oracle(wl.with_(walkoff_sh=0.0, walkoff_f=0.0), a0, b0)
+    walk = run_oracle(wl, a0, b0)
+    assert rel(walk["a_sh"], plain["a_sh"]) > 1e-2
