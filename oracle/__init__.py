@@ -13,5 +13,8 @@ Contents
   beams    focused Gaussian input beam (Sec. 2.1, Eqs. 5-6)
   pins     closed forms and quadratures that pin the oracle to the physics
            (Boyd-Kleinman focusing function, Eq. 17; plane-wave laws)
+  thermal  steady-state heat equation (Sec. 2.2, finite differences of
+           Sec. 3.2) by a sparse direct solve, the heat source of the fields,
+           and the self-consistent field <-> temperature loop (Sec. 4 flowchart)
 """
-from . import ssfm, beams, pins, adjoint  # noqa: F401
+from . import ssfm, beams, pins, adjoint, thermal  # noqa: F401
