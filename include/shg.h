@@ -122,6 +122,18 @@ int shg_propagate(shg_plan *plan, void *a_f, void *a_sh, const double *dk_z,
                   const void *temp, int32_t s_begin, int32_t s_end,
                   void *workspace, double *powers, void *stream);
 
+/* The whole march (steps [0, nz)) as shg_propagate, also writing the heat
+ * source of Sec. 2.2, q = sum_j alpha_j I_j + beta_j I_j^2 with
+ * I_j = eps0 c n_j |A_j|^2 / 2 [W/m^3], of the fields at every step boundary
+ * z_l = l dz, l = 0..nz (the input, the state between the two half-steps of
+ * consecutive steps, and the output).  This is the source the heat equation
+ * needs for the self-consistent loop.
+ *   heat  [nz + 1][ny][nx] in the plan's real type (required)
+ * Other arguments and errors as shg_propagate. */
+int shg_propagate_heat(shg_plan *plan, void *a_f, void *a_sh, const double *dk_z,
+                       const void *temp, void *heat, void *workspace, double *powers,
+                       void *stream);
+
 /* Gradient of a real loss L through the whole march (steps [0, nz)).
  * The loss is L = Re<g_f_out, A_F(L)> + Re<g_sh_out, A_SH(L)>
  *               + w[0] P_F(L) + w[1] P_SH(L)  (to first order),
@@ -202,6 +214,80 @@ int shg_plan_describe(const shg_plan *plan, char *buf, size_t len);
 /* Message of the last failed call on this thread ("" if none).  Valid until
  * the next call on this thread. */
 const char *shg_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Steady-state heat equation and the self-consistent loop (Sec. 2.2, the
+ * finite differences of Sec. 3.2 and the flowchart of Sec. 4).
+ *
+ * k lap T + q = 0 with q the heat source of shg_propagate_heat, on the nodes
+ * of the field grid: nx x ny transverse samples (the x and y faces of the
+ * crystal are the first and last samples) times nz + 1 planes z_l = l dz.
+ * Nodes on an oven face are held at t_oven (edges and corners included); air
+ * faces obey -k dT/dn = h_conv (T - t_inf); insulated faces have no flux.
+ * Every other node obeys the second-order 7-point equation, with the outside
+ * neighbour of a face node removed through the central difference of its
+ * boundary condition.  The solver is Jacobi-preconditioned conjugate
+ * gradients on the control-volume (symmetric) form of those equations, in the
+ * plan's real type with FP64 reductions; it synchronises the stream to test
+ * convergence, so it cannot be captured into a graph.
+ * Temperatures are arrays in the plan's real type: t_nodes [nz + 1][ny][nx]
+ * and the mid-planes t_mid [nz][ny][nx] = (T_l + T_{l+1}) / 2 that
+ * shg_propagate takes as its temperature field. */
+typedef struct shg_thermal shg_thermal;
+
+enum { SHG_FACE_AIR = 0, SHG_FACE_OVEN = 1, SHG_FACE_INSULATED = 2 };
+
+typedef struct {
+  int32_t nx, ny, nz;     /* the field grid; nodes nx x ny x (nz + 1)          */
+  int32_t faces[6];       /* x-, x+, y-, y+, z-, z+: SHG_FACE_*                 */
+  int32_t reserved;       /* 0                                                  */
+  double lx, ly, lcr;     /* as in shg_params [m]                               */
+  double k_th;            /* thermal conductivity [W/(m K)]                     */
+  double h_conv;          /* convection coefficient of air faces [W/(m^2 K)]    */
+  double t_inf;           /* air temperature [K]                                */
+  double t_oven;          /* oven temperature [K]                               */
+} shg_thermal_params;
+
+/* Errors: SHG_EINVAL (grid as for shg_plan_create, k_th <= 0, h_conv < 0,
+ * non-finite temperatures, unknown face kind, or no oven face and no cooled
+ * air face, which leaves T undetermined), SHG_ENOMEM.  Allocates no device
+ * memory. */
+int shg_thermal_create(shg_thermal **out, const shg_thermal_params *p, shg_dtype dtype);
+int shg_thermal_destroy(shg_thermal *th);
+
+/* Device workspace of shg_thermal_solve and shg_self_consistent: seven node
+ * vectors (nx ny (nz + 1) reals each) plus a few KB. */
+size_t shg_thermal_workspace_bytes(const shg_thermal *th);
+
+/* Solve for T with source heat [nz + 1][ny][nx] [W/m^3].
+ *   t_nodes    in: initial guess (warm start); out: solution
+ *   t_mid      out: mid-plane temperatures, or NULL
+ *   tol        stop when |r| <= tol |b| (2-norms of the weighted system)
+ *   iterations, residual  out (host pointers, may be NULL)
+ * Returns after the solve (the host waits on the stream).  Errors:
+ * SHG_ESTATE, SHG_EINVAL (NULL arrays or workspace, tol <= 0, max_iter < 1),
+ * SHG_EDEVICE (including a diverged iteration). */
+int shg_thermal_solve(shg_thermal *th, const void *heat, void *t_nodes, void *t_mid, double tol,
+                      int32_t max_iter, void *workspace, int32_t *iterations, double *residual,
+                      void *stream);
+
+/* The self-consistent loop: T from q = 0, then repeatedly march the input
+ * (a_f0, a_sh0) with the mid-plane field of T (per-cell dk(T) and thermal
+ * lens), take its heat source and solve for T again, until the largest change
+ * of T between two solves is <= tol_t or max_outer marches have run.
+ *   a_f, a_sh   out: the fields of the last march
+ *   t_nodes     in: initial guess of the first solve; out: final T
+ *   t_mid       out: mid-planes of the final T
+ *   solve_tol, max_iter  passed to each solve
+ *   workspace   shg_thermal_workspace_bytes(th) bytes (the march uses the
+ *               plan's own forward workspace)
+ *   outer, change  out (host): marches run and the last largest change [K]
+ * The thermal grid (nx, ny, nz, lx, ly, lcr) and dtype must match the plan's.
+ * Errors: as shg_thermal_solve and shg_propagate. */
+int shg_self_consistent(shg_plan *plan, shg_thermal *th, const void *a_f0, const void *a_sh0,
+                        const double *dk_z, void *a_f, void *a_sh, void *t_nodes, void *t_mid,
+                        double tol_t, int32_t max_outer, double solve_tol, int32_t max_iter,
+                        void *workspace, int32_t *outer, double *change, void *stream);
 
 #ifdef __cplusplus
 }

@@ -40,13 +40,28 @@ class ShgParams(ctypes.Structure):
                 ("walkoff_sh", ctypes.c_double)]
 
 
+SHG_FACE_AIR, SHG_FACE_OVEN, SHG_FACE_INSULATED = 0, 1, 2
+FACE_NAMES = ("x-", "x+", "y-", "y+", "z-", "z+")
+FACE_KINDS = {"air": SHG_FACE_AIR, "oven": SHG_FACE_OVEN, "insulated": SHG_FACE_INSULATED}
+
+
+class ThermalParams(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("faces", ctypes.c_int32 * 6), ("reserved", ctypes.c_int32),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lcr", ctypes.c_double),
+                ("k_th", ctypes.c_double), ("h_conv", ctypes.c_double), ("t_inf", ctypes.c_double),
+                ("t_oven", ctypes.c_double)]
+
+
 _VP = ctypes.c_void_p
 _I32 = ctypes.c_int32
+_F64 = ctypes.c_double
 _SIGS = {
     "shg_plan_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(ShgParams), ctypes.c_int]),
     "shg_plan_destroy": (ctypes.c_int, [_VP]),
     "shg_workspace_bytes": (ctypes.c_size_t, [_VP, ctypes.c_int]),
     "shg_propagate": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP]),
+    "shg_propagate_heat": (ctypes.c_int, [_VP] * 9),
     "shg_propagate_adjoint": (ctypes.c_int, [_VP] * 16 + [_VP]),
     "shg_propagate_batch": (ctypes.c_int, [_I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "shg_batch_workspace_bytes": (ctypes.c_size_t, [_I32, _VP]),
@@ -56,6 +71,15 @@ _SIGS = {
     "shg_plan_set_batch_schedule": (ctypes.c_int, [_VP, _I32, _I32, _I32, _I32]),
     "shg_plan_kernel_times": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double)]),
     "shg_last_error": (ctypes.c_char_p, []),
+    "shg_thermal_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(ThermalParams),
+                                          ctypes.c_int]),
+    "shg_thermal_destroy": (ctypes.c_int, [_VP]),
+    "shg_thermal_workspace_bytes": (ctypes.c_size_t, [_VP]),
+    "shg_thermal_solve": (ctypes.c_int, [_VP, _VP, _VP, _VP, _F64, _I32, _VP,
+                                         ctypes.POINTER(_I32), ctypes.POINTER(_F64), _VP]),
+    "shg_self_consistent": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _F64, _I32,
+                                           _F64, _I32, _VP, ctypes.POINTER(_I32),
+                                           ctypes.POINTER(_F64), _VP]),
 }
 
 _lib = None
@@ -204,6 +228,24 @@ class Plan:
             _ptr(powers, "powers", torch.float64), _stream(stream)))
         return powers
 
+    def propagate_heat(self, a_f, a_sh, dk_z=None, temp=None, heat=None, workspace=None,
+                       powers=None, stream=None):
+        """Whole march in place, also writing the heat source at the nz + 1 step
+        boundaries.  Returns (heat [nz+1, ny, nx], powers)."""
+        torch = _torch()
+        p = self.params
+        if heat is None:
+            heat = torch.empty((p["nz"] + 1, p["ny"], p["nx"]), dtype=self.real_dtype,
+                               device=a_f.device)
+        if powers is None:
+            powers = torch.empty(2, dtype=torch.float64, device=a_f.device)
+        _check(load_library().shg_propagate_heat(
+            self.handle, self._field(a_f, "a_f"), self._field(a_sh, "a_sh"),
+            _ptr(dk_z, "dk_z", torch.float64), _ptr(temp, "temp", self.real_dtype),
+            _ptr(heat, "heat", self.real_dtype), _ptr(workspace, "workspace"),
+            _ptr(powers, "powers", torch.float64), _stream(stream)))
+        return heat, powers
+
     def adjoint(self, a_f_in, a_sh_in, g_f_out=None, g_sh_out=None, power_weights=None, dk_z=None,
                 temp=None, want_dk=False, want_t=False, workspace=None, stream=None):
         """Forward + reverse march.  Returns a dict with g_f, g_sh (gradients at
@@ -268,3 +310,110 @@ def propagate_batch(plans: Sequence[Plan], a_f: Sequence, a_sh: Sequence, dk_z: 
     _check(load_library().shg_propagate_batch(n, hp, fa, fs, dk, _ptr(workspace, "workspace"),
                                               _ptr(powers, "powers", torch.float64), _stream(stream)))
     return powers
+
+
+def make_thermal_params(params: dict, k_th: float, h_conv: float, t_inf: float, t_oven: float,
+                        faces: dict) -> ThermalParams:
+    """faces: face name ("x-" .. "z+") -> "oven" | "air" | "insulated" (default air)."""
+    tp = ThermalParams()
+    tp.nx, tp.ny, tp.nz = int(params["nx"]), int(params["ny"]), int(params["nz"])
+    for i, f in enumerate(FACE_NAMES):
+        tp.faces[i] = FACE_KINDS[faces.get(f, "air")]
+    tp.reserved = 0
+    tp.lx, tp.ly, tp.lcr = params["lx"], params["ly"], params["lcr"]
+    tp.k_th, tp.h_conv, tp.t_inf, tp.t_oven = k_th, h_conv, t_inf, t_oven
+    return tp
+
+
+class Thermal:
+    """Owns an shg_thermal: the heat-equation solver on the nodes of a field grid."""
+
+    def __init__(self, params: dict, k_th: float, h_conv: float, t_inf: float, t_oven: float,
+                 faces: dict, dtype: str = "c64"):
+        lib = load_library()
+        self.params = dict(params)
+        self.dtype = dtype
+        self.t_oven = t_oven
+        self._cp = make_thermal_params(params, k_th, h_conv, t_inf, t_oven, faces)
+        h = _VP()
+        _check(lib.shg_thermal_create(ctypes.byref(h), ctypes.byref(self._cp),
+                                      SHG_C64 if dtype == "c64" else SHG_C128))
+        self.handle = h
+        self._ws = None
+
+    @property
+    def real_dtype(self):
+        torch = _torch()
+        return torch.float32 if self.dtype == "c64" else torch.float64
+
+    @property
+    def node_shape(self):
+        return (self.params["nz"] + 1, self.params["ny"], self.params["nx"])
+
+    def workspace_bytes(self) -> int:
+        return int(load_library().shg_thermal_workspace_bytes(self.handle))
+
+    def workspace(self, device=None):
+        torch = _torch()
+        n = self.workspace_bytes()
+        if self._ws is None or self._ws.numel() < n:
+            self._ws = torch.empty(n, dtype=torch.uint8, device=device or "cuda")
+        return self._ws
+
+    def solve(self, heat, t_nodes=None, t_mid=None, tol: float = 1e-6, max_iter: int = 20000,
+              workspace=None, stream=None):
+        """Solve k lap T + heat = 0.  t_nodes is the warm start (default T_oven
+        everywhere) and receives T.  Returns (t_nodes, t_mid, iterations, residual)."""
+        torch = _torch()
+        dev = heat.device
+        if t_nodes is None:
+            t_nodes = torch.full(self.node_shape, self.t_oven, dtype=self.real_dtype, device=dev)
+        if t_mid is None:
+            n = self.node_shape
+            t_mid = torch.empty((n[0] - 1, n[1], n[2]), dtype=self.real_dtype, device=dev)
+        it = _I32()
+        res = _F64()
+        _check(load_library().shg_thermal_solve(
+            self.handle, _ptr(heat, "heat", self.real_dtype), _ptr(t_nodes, "t_nodes", self.real_dtype),
+            _ptr(t_mid, "t_mid", self.real_dtype), float(tol), int(max_iter),
+            _ptr(workspace if workspace is not None else self.workspace(dev), "workspace"),
+            ctypes.byref(it), ctypes.byref(res), _stream(stream)))
+        return t_nodes, t_mid, int(it.value), float(res.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().shg_thermal_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def self_consistent(plan: Plan, thermal: Thermal, a_f0, a_sh0, dk_z=None, t_nodes=None,
+                    tol_t: float = 1e-4, max_outer: int = 30, solve_tol: float = 1e-6,
+                    max_iter: int = 20000, workspace=None, stream=None):
+    """The self-consistent field <-> temperature loop.  Returns a dict with the
+    fields of the last march, t_nodes, t_mid, the number of marches and the last
+    largest change of T."""
+    torch = _torch()
+    dev = a_f0.device
+    a_f = torch.empty_like(a_f0)
+    a_sh = torch.empty_like(a_sh0)
+    if t_nodes is None:
+        t_nodes = torch.full(thermal.node_shape, thermal.t_oven, dtype=thermal.real_dtype, device=dev)
+    n = thermal.node_shape
+    t_mid = torch.empty((n[0] - 1, n[1], n[2]), dtype=thermal.real_dtype, device=dev)
+    outer = _I32()
+    change = _F64()
+    _check(load_library().shg_self_consistent(
+        plan.handle, thermal.handle, plan._field(a_f0, "a_f0"), plan._field(a_sh0, "a_sh0"),
+        _ptr(dk_z, "dk_z", torch.float64), plan._field(a_f, "a_f"), plan._field(a_sh, "a_sh"),
+        _ptr(t_nodes, "t_nodes", thermal.real_dtype), _ptr(t_mid, "t_mid", thermal.real_dtype),
+        float(tol_t), int(max_outer), float(solve_tol), int(max_iter),
+        _ptr(workspace if workspace is not None else thermal.workspace(dev), "workspace"),
+        ctypes.byref(outer), ctypes.byref(change), _stream(stream)))
+    return {"a_f": a_f, "a_sh": a_sh, "t_nodes": t_nodes, "t_mid": t_mid,
+            "outer": int(outer.value), "change": float(change.value)}

@@ -160,7 +160,19 @@ struct RowArgs {
   R* psi;                 // [ny][nx] in: Psi at the oldest step touched; out: at the newest
   R* tap_psi;             // optional: Psi_{s_second} (adjoint recompute)
   R t_ref, ddk, lens_f, lens_sh, dz;
+  // optional heat source (Sec. 2.2) of the state at this pass's step boundary
+  // (after the second half-step of s_second, before the first of s_first)
+  R* heat;                // [ny][nx] plane, or null
+  R hi_f, hi_sh;          // eps0 c n_j / 2: intensity per |A_j|^2
+  R ha_f, hb_f, ha_sh, hb_sh;   // alpha_j, beta_j
 };
+
+// q = sum_j alpha_j I_j + beta_j I_j^2, I_j = (eps0 c n_j / 2) |A_j|^2
+template <typename R>
+__device__ __forceinline__ R heat_density(cx<R> a, cx<R> b, const RowArgs<R>& p) {
+  const R i_f = p.hi_f * norm2(a), i_s = p.hi_sh * norm2(b);
+  return i_f * (p.ha_f + p.hb_f * i_f) + i_s * (p.ha_sh + p.hb_sh * i_s);
+}
 
 template <int G, int WG>
 struct RowShape {
@@ -242,6 +254,7 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
         rk4_cell_t(va[m], vb[m], c, p.tf, p.ts, p.h, und);
         psi += dT * p.dz;
       }
+      if (p.heat) p.heat[idx] = heat_density(va[m], vb[m], p);
       if (p.s_first >= 0) {
         const R dT = p.temp[(size_t)p.s_first * n2 + idx] - p.t_ref;
         const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, p.ddk, psi, dT,
@@ -257,6 +270,10 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
       const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);
 #pragma unroll
       for (int m = 0; m < E; ++m) rk4_cell(va[m], vb[m], c, p.tf, p.ts, p.h, und);
+    }
+    if (p.heat) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) p.heat[row + t + G * m] = heat_density(va[m], vb[m], p);
     }
     if (p.s_first >= 0) {
       const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks);
@@ -379,6 +396,7 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
       rk4_cell_t(a, b, c, p.tf, p.ts, p.h, und);
       psi += dT * p.dz;
     }
+    if (p.heat) p.heat[idx] = heat_density(a, b, p);
     if (p.s_first >= 0) {
       const R dT = p.temp[(size_t)p.s_first * n2 + idx] - p.t_ref;
       const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, p.ddk, psi, dT,
@@ -391,6 +409,7 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
       const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);
       rk4_cell(a, b, c, p.tf, p.ts, p.h, und);
     }
+    if (p.heat) p.heat[idx] = heat_density(a, b, p);
     if (p.s_first >= 0) {
       const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks);
       rk4_cell(a, b, c, p.tf, p.ts, p.h, und);

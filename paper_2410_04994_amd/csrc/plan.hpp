@@ -15,12 +15,13 @@ struct GraphKey {
   const void* b;
   const void* dk;
   const void* temp;
+  const void* heat;
   const void* ws;
   const void* powers;
   int s0, s1;
   int re, rw, ce, ct;
   bool operator==(const GraphKey& o) const {
-    return a == o.a && b == o.b && dk == o.dk && temp == o.temp && ws == o.ws &&
+    return a == o.a && b == o.b && dk == o.dk && temp == o.temp && heat == o.heat && ws == o.ws &&
            powers == o.powers && s0 == o.s0 &&
            s1 == o.s1 && re == o.re && rw == o.rw && ce == o.ce && ct == o.ct;
   }
@@ -78,6 +79,8 @@ struct Plan {
 // the per-cell accumulated (T - T_ref) dz buffer holding Psi at s0 (when NULL
 // the workspace buffer is used and initialised from temp); tap_psi receives
 // Psi at the start of each step s at tap_psi + (s - s0) * nx * ny.
+// heat (optional) receives the heat source of the state at every step
+// boundary l = s0..s1 at heat + l * nx * ny (the plan's real type).
 struct FwdIO {
   const void* a_in;
   const void* b_in;
@@ -89,6 +92,7 @@ struct FwdIO {
   const void* temp = nullptr;
   void* psi = nullptr;
   void* tap_psi = nullptr;
+  void* heat = nullptr;
 };
 
 // shg.hip
@@ -103,6 +107,8 @@ int enqueue_forward(Plan& pl, void* a, void* b, const double* dk_z, int s0, int 
 int enqueue_forward_io(Plan& pl, const FwdIO& io, const double* dk_z, int s0, int s1, void* ws,
                        double* powers, hipStream_t st, bool make_phase);
 int ensure_own_ws(Plan& pl, size_t bytes);
+int propagate(Plan& pl, void* a_f, void* a_sh, const double* dk_z, const void* temp, int s0,
+              int s1, void* ws, double* powers, hipStream_t st, void* heat);
 size_t align256(size_t v);
 int launch_col(Plan& pl, void* a, void* b, int conj, hipStream_t st);
 bool row_supported(const Plan& pl, int e, int wg, int* rows);

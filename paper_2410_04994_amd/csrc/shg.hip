@@ -496,6 +496,13 @@ static int enqueue_forward_t(Plan& pl, const FwdIO& io, const double* dk_z, int 
   ra.ts = (R)(pl.tpa_sh / 2.0);
   ra.h = (R)(pl.dz / 2.0);
   ra.undepleted = (p.flags & SHG_UNDEPLETED) ? 1 : 0;
+  R* heat = (R*)io.heat;
+  ra.hi_f = (R)(kEps0 * kC * p.n_f / 2.0);
+  ra.hi_sh = (R)(kEps0 * kC * p.n_sh / 2.0);
+  ra.ha_f = (R)p.alpha_f;
+  ra.hb_f = (R)p.beta_f;
+  ra.ha_sh = (R)p.alpha_sh;
+  ra.hb_sh = (R)p.beta_sh;
   if (io.temp) {
     ra.temp = (const R*)io.temp;
     ra.psi = io.psi ? (R*)io.psi : psi;
@@ -534,6 +541,7 @@ static int enqueue_forward_t(Plan& pl, const FwdIO& io, const double* dk_z, int 
   ra.inv_in = 0;
   ra.fwd_out = 1;
   ra.partials = nullptr;
+  ra.heat = heat ? heat + (size_t)s0 * n2 : nullptr;
   if (!row_dispatch<R>(p.nx, pl.row_e, pl.row_wg, &ra, st, &rows, &tm))
     return fail(SHG_EUNSUPPORTED, "row schedule e=%d wg=%d not built", pl.row_e, pl.row_wg);
   for (int s = s0; s < s1; ++s) {
@@ -552,6 +560,7 @@ static int enqueue_forward_t(Plan& pl, const FwdIO& io, const double* dk_z, int 
     ra.inv_in = 1;
     ra.fwd_out = last ? 0 : 1;
     ra.partials = (last && powers) ? partials : nullptr;
+    ra.heat = heat ? heat + (size_t)(s + 1) * n2 : nullptr;
     row_dispatch<R>(p.nx, pl.row_e, pl.row_wg, &ra, st, &rows, &tm);
   }
   if (powers) {
@@ -610,9 +619,10 @@ int enqueue_forward(Plan& pl, void* a, void* b, const double* dk_z, int s0, int 
 }
 
 int enqueue_forward_temp(Plan& pl, void* a, void* b, const double* dk_z, const void* temp, int s0,
-                         int s1, void* ws, double* powers, hipStream_t st) {
+                         int s1, void* ws, double* powers, hipStream_t st, void* heat) {
   FwdIO io{a, b, a, b, a, b, nullptr};
   io.temp = temp;
+  io.heat = heat;
   return enqueue_forward_io(pl, io, dk_z, s0, s1, ws, powers, st, true);
 }
 
@@ -636,14 +646,15 @@ int ensure_own_ws(Plan& pl, size_t bytes) {
 // Replays a cached graph of the whole launch sequence when the arguments are
 // the same as last time; otherwise captures a new one on a private stream.
 static int run_forward(Plan& pl, void* a, void* b, const double* dk_z, const void* temp, int s0,
-                       int s1, void* ws, double* powers, hipStream_t st) {
+                       int s1, void* ws, double* powers, hipStream_t st, void* heat) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   hipError_t e = hipStreamIsCapturing(st, &cs);
   if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
   const bool use_graph = !(pl.p.flags & SHG_NO_GRAPH) && !pl.timing &&
                          cs == hipStreamCaptureStatusNone && (s1 - s0) >= 2;
-  if (!use_graph) return enqueue_forward_temp(pl, a, b, dk_z, temp, s0, s1, ws, powers, st);
-  GraphKey key{a, b, dk_z, temp, ws, powers, s0, s1, pl.row_e, pl.row_wg, pl.col_e, pl.col_tc};
+  if (!use_graph) return enqueue_forward_temp(pl, a, b, dk_z, temp, s0, s1, ws, powers, st, heat);
+  GraphKey key{a,  b,  dk_z, temp, heat, ws, powers, s0, s1, pl.row_e, pl.row_wg, pl.col_e,
+               pl.col_tc};
   if (!pl.gexec || !(key == pl.gkey)) {
     if (pl.gexec) {
       (void)hipGraphExecDestroy(pl.gexec);
@@ -655,7 +666,7 @@ static int run_forward(Plan& pl, void* a, void* b, const double* dk_z, const voi
     }
     e = hipStreamBeginCapture(pl.cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    int rc = enqueue_forward_temp(pl, a, b, dk_z, temp, s0, s1, ws, powers, pl.cap_stream);
+    int rc = enqueue_forward_temp(pl, a, b, dk_z, temp, s0, s1, ws, powers, pl.cap_stream, heat);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(pl.cap_stream, &g);
     if (rc != SHG_OK) {
@@ -690,7 +701,7 @@ int sticky_device_error() {
 }
 
 int propagate(Plan& pl, void* a_f, void* a_sh, const double* dk_z, const void* temp, int s0,
-              int s1, void* ws, double* powers, hipStream_t st) {
+              int s1, void* ws, double* powers, hipStream_t st, void* heat) {
   if (!a_f || !a_sh) return fail(SHG_EINVAL, "a_f and a_sh must be non-NULL device pointers");
   if (!(0 <= s0 && s0 < s1 && s1 <= pl.p.nz))
     return fail(SHG_EINVAL, "step range [%d, %d) not within [0, nz=%d]", s0, s1, pl.p.nz);
@@ -700,7 +711,7 @@ int propagate(Plan& pl, void* a_f, void* a_sh, const double* dk_z, const void* t
     if ((rc = ensure_own_ws(pl, forward_ws_bytes(pl)))) return rc;
     ws = pl.own_ws;
   }
-  return run_forward(pl, a_f, a_sh, dk_z, temp, s0, s1, ws, powers, st);
+  return run_forward(pl, a_f, a_sh, dk_z, temp, s0, s1, ws, powers, st, heat);
 }
 
 }  // namespace shg
@@ -757,7 +768,19 @@ int shg_propagate(shg_plan* plan, void* a_f, void* a_sh, const double* dk_z, con
   if (rc) return rc;
   Plan* pl = reinterpret_cast<Plan*>(plan);
   rc = propagate(*pl, a_f, a_sh, dk_z, temp, s_begin, s_end, workspace, powers,
-                 (hipStream_t)stream);
+                 (hipStream_t)stream, nullptr);
+  return rc ? rc : ok();
+}
+
+int shg_propagate_heat(shg_plan* plan, void* a_f, void* a_sh, const double* dk_z,
+                       const void* temp, void* heat, void* workspace, double* powers,
+                       void* stream) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!heat) return fail(SHG_EINVAL, "heat must be a non-NULL device pointer");
+  Plan* pl = reinterpret_cast<Plan*>(plan);
+  rc = propagate(*pl, a_f, a_sh, dk_z, temp, 0, pl->p.nz, workspace, powers,
+                 (hipStream_t)stream, heat);
   return rc ? rc : ok();
 }
 

@@ -1,0 +1,322 @@
+// Heat equation and the self-consistent field <-> temperature loop: thermal
+// plans, the Jacobi-preconditioned conjugate-gradient driver and the loop of
+// the flowchart in Sec. 4 (q = 0 -> T -> march with dk(T) -> q -> T -> ...).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "plan.hpp"
+#include "thermal_kernels.hpp"
+
+namespace shg {
+
+struct Therm {
+  static constexpr uint64_t kMagic = 0x5348475f54484552ull;  // "SHG_THER"
+  uint64_t magic = 0;
+  shg_thermal_params p{};
+  shg_dtype dtype = SHG_C64;
+  int device = 0;
+  ThermGeom g{};
+  int nblk = 0;             // blocks of the grid-stride kernels
+  size_t real_bytes = 4;
+};
+
+// Workspace: theta, r, p0, p1, Ap, t_prev, heat (one node vector each), block
+// partials, device scalars.
+struct ThermLayout {
+  size_t theta, r, p0, p1, ap, t_prev, heat, part, sc, total;
+};
+
+static ThermLayout therm_layout(const Therm& th) {
+  ThermLayout L{};
+  const size_t vec = align256(th.g.n * th.real_bytes);
+  size_t off = 0;
+  for (size_t* f : {&L.theta, &L.r, &L.p0, &L.p1, &L.ap, &L.t_prev, &L.heat}) {
+    *f = off;
+    off += vec;
+  }
+  L.part = off;
+  off += align256((size_t)th.nblk * 2 * sizeof(double));
+  L.sc = off;
+  off += align256(16 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+static bool is_pow2_grid(int v) { return v >= 16 && v <= 512 && (v & (v - 1)) == 0; }
+
+static int validate_thermal(const shg_thermal_params* p) {
+  if (!is_pow2_grid(p->nx) || !is_pow2_grid(p->ny))
+    return fail(SHG_EINVAL, "nx=%d ny=%d: each must be a power of two in [16, 512]", p->nx, p->ny);
+  if (p->nz < 1) return fail(SHG_EINVAL, "nz=%d must be >= 1", p->nz);
+  if (!(p->lx > 0 && p->ly > 0 && p->lcr > 0) || !std::isfinite(p->lx) || !std::isfinite(p->ly) ||
+      !std::isfinite(p->lcr))
+    return fail(SHG_EINVAL, "lx, ly, lcr must be finite and positive");
+  if (!(p->k_th > 0) || !std::isfinite(p->k_th))
+    return fail(SHG_EINVAL, "k_th must be finite and positive");
+  if (!(p->h_conv >= 0) || !std::isfinite(p->h_conv))
+    return fail(SHG_EINVAL, "h_conv must be finite and >= 0");
+  if (!std::isfinite(p->t_inf) || !std::isfinite(p->t_oven))
+    return fail(SHG_EINVAL, "t_inf and t_oven must be finite");
+  bool oven = false, cooled = false;
+  for (int f = 0; f < 6; ++f) {
+    if (p->faces[f] != SHG_FACE_AIR && p->faces[f] != SHG_FACE_OVEN &&
+        p->faces[f] != SHG_FACE_INSULATED)
+      return fail(SHG_EINVAL, "faces[%d]=%d is not SHG_FACE_AIR/OVEN/INSULATED", f, p->faces[f]);
+    oven |= p->faces[f] == SHG_FACE_OVEN;
+    cooled |= p->faces[f] == SHG_FACE_AIR && p->h_conv > 0;
+  }
+  if (!oven && !cooled)
+    return fail(SHG_EINVAL, "no oven face and no convective face: the temperature is not fixed");
+  return SHG_OK;
+}
+
+static int ilog2(size_t v) {
+  int k = 0;
+  while (((size_t)1 << k) < v) ++k;
+  return k;
+}
+
+static void build_geom(Therm& th) {
+  const shg_thermal_params& p = th.p;
+  ThermGeom& g = th.g;
+  g.nx = p.nx;
+  g.ny = p.ny;
+  g.nzn = p.nz + 1;
+  g.log2_nx = ilog2((size_t)p.nx);
+  g.log2_plane = ilog2((size_t)p.nx * p.ny);
+  const double h[3] = {p.lx / p.nx, p.ly / p.ny, p.lcr / p.nz};
+  const double beta = p.h_conv / p.k_th;
+  for (int d = 0; d < 3; ++d) g.ih2[d] = 1.0 / (h[d] * h[d]);
+  for (int f = 0; f < 6; ++f) {
+    g.face[f] = p.faces[f];
+    const bool air = p.faces[f] == SHG_FACE_AIR;
+    g.conv[f] = air ? 2.0 * beta / h[f / 2] : 0.0;
+    g.src_conv[f] = air ? 2.0 * beta * (p.t_oven - p.t_inf) / h[f / 2] : 0.0;
+  }
+  g.inv_k = 1.0 / p.k_th;
+  g.n = (size_t)p.nx * p.ny * (p.nz + 1);
+  th.nblk = (int)std::min<size_t>(2048, (g.n + 255) / 256);
+  th.real_bytes = th.dtype == SHG_C64 ? 4 : 8;
+}
+
+static int check_therm(const shg_thermal* t) {
+  if (!t) return fail(SHG_ESTATE, "thermal plan is NULL");
+  const Therm* th = reinterpret_cast<const Therm*>(t);
+  if (th->magic != Therm::kMagic) return fail(SHG_ESTATE, "not a live thermal plan");
+  return SHG_OK;
+}
+
+// Conjugate gradients on theta = T - T_oven, warm-started from t_nodes.
+template <typename R>
+static int solve_t(Therm& th, const R* heat, R* t_nodes, R* t_mid, double tol, int max_iter,
+                   char* ws, int* iters_out, double* resid_out, hipStream_t st) {
+  const ThermLayout L = therm_layout(th);
+  const ThermGeom& g = th.g;
+  R* theta = (R*)(ws + L.theta);
+  R* r = (R*)(ws + L.r);
+  R* pc = (R*)(ws + L.p0);
+  R* pn = (R*)(ws + L.p1);
+  R* ap = (R*)(ws + L.ap);
+  double* part = (double*)(ws + L.part);
+  double* sc = (double*)(ws + L.sc);
+  const dim3 grid(th.nblk), blk(256);
+  hipLaunchKernelGGL((th_init<R>), grid, blk, 0, st, g, (const R*)t_nodes, th.p.t_oven, theta, pc);
+  hipLaunchKernelGGL((th_residual<R>), grid, blk, 0, st, g, heat, (const R*)theta, r, part);
+  hipLaunchKernelGGL(th_scalars, dim3(1), blk, 0, st, (const double*)part, th.nblk, 0, sc);
+  double hs[kCount];
+  hipError_t e = hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "thermal residual");
+  const double bnorm = std::sqrt(hs[kBb]);
+  int it = 0;
+  double res = hs[kRz] > 0.0 ? 1.0 : 0.0;
+  constexpr int kCheck = 16;
+  while (it < max_iter && hs[kRz] > 0.0 && bnorm > 0.0) {
+    const int chunk = std::min(kCheck, max_iter - it);
+    for (int k = 0; k < chunk; ++k) {
+      hipLaunchKernelGGL((th_direction_apply<R>), grid, blk, 0, st, g, (const R*)r, (const R*)pc,
+                         pn, ap, (const double*)sc, part);
+      hipLaunchKernelGGL(th_scalars, dim3(1), blk, 0, st, (const double*)part, th.nblk, 1, sc);
+      hipLaunchKernelGGL((th_update<R>), grid, blk, 0, st, g, theta, r, (const R*)pn,
+                         (const R*)ap, (const double*)sc, part);
+      hipLaunchKernelGGL(th_scalars, dim3(1), blk, 0, st, (const double*)part, th.nblk, 2, sc);
+      std::swap(pc, pn);
+    }
+    it += chunk;
+    e = hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "thermal iteration");
+    res = std::sqrt(std::max(hs[kRr], 0.0)) / bnorm;
+    if (!std::isfinite(res)) return fail(SHG_EDEVICE, "thermal solve diverged (residual %g)", res);
+    if (res <= tol) break;
+  }
+  if (bnorm == 0.0) {
+    // no source and no convective drive: theta = 0 everywhere
+    e = hipMemsetAsync(theta, 0, g.n * sizeof(R), st);
+    if (e != hipSuccess) return hip_fail(e, "clearing theta");
+    res = 0.0;
+  }
+  hipLaunchKernelGGL((th_finish<R>), grid, blk, 0, st, g, (const R*)theta, th.p.t_oven, t_nodes);
+  if (t_mid) {
+    const size_t plane = (size_t)g.nx * g.ny;
+    hipLaunchKernelGGL((th_midplanes<R>), grid, blk, 0, st, (const R*)t_nodes, plane,
+                       plane * (size_t)(g.nzn - 1), t_mid);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "thermal kernel launch");
+  if (iters_out) *iters_out = it;
+  if (resid_out) *resid_out = res;
+  return SHG_OK;
+}
+
+static int solve_any(Therm& th, const void* heat, void* t_nodes, void* t_mid, double tol,
+                     int max_iter, void* ws, int* iters, double* resid, hipStream_t st) {
+  if (th.dtype == SHG_C64)
+    return solve_t<float>(th, (const float*)heat, (float*)t_nodes, (float*)t_mid, tol, max_iter,
+                          (char*)ws, iters, resid, st);
+  return solve_t<double>(th, (const double*)heat, (double*)t_nodes, (double*)t_mid, tol, max_iter,
+                         (char*)ws, iters, resid, st);
+}
+
+template <typename R>
+static int max_change(Therm& th, const void* a, const void* b, char* ws, double* out,
+                      hipStream_t st) {
+  const ThermLayout L = therm_layout(th);
+  double* part = (double*)(ws + L.part);
+  double* sc = (double*)(ws + L.sc);
+  hipLaunchKernelGGL((th_max_change<R>), dim3(th.nblk), dim3(256), 0, st, (const R*)a,
+                     (const R*)b, th.g.n, part);
+  hipLaunchKernelGGL(th_max_final, dim3(1), dim3(256), 0, st, (const double*)part, th.nblk,
+                     sc + kCount);
+  hipError_t e = hipMemcpyAsync(out, sc + kCount, sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e == hipSuccess ? SHG_OK : hip_fail(e, "temperature change");
+}
+
+static int self_consistent(Plan& pl, Therm& th, const void* a_f0, const void* a_sh0,
+                           const double* dk_z, void* a_f, void* a_sh, void* t_nodes, void* t_mid,
+                           double tol_t, int max_outer, double solve_tol, int max_iter, char* ws,
+                           int* outer_out, double* change_out, hipStream_t st) {
+  const ThermLayout L = therm_layout(th);
+  void* heat = ws + L.heat;
+  void* t_prev = ws + L.t_prev;
+  const size_t vec = th.g.n * th.real_bytes;
+  const size_t field = (size_t)pl.p.nx * pl.p.ny * 2 * th.real_bytes;
+  // q = 0 -> T
+  hipError_t e = hipMemsetAsync(heat, 0, vec, st);
+  if (e != hipSuccess) return hip_fail(e, "clearing the heat source");
+  int rc = solve_any(th, heat, t_nodes, t_mid, solve_tol, max_iter, ws, nullptr, nullptr, st);
+  if (rc) return rc;
+  double change = 0.0;
+  int k = 0;
+  while (k < max_outer) {
+    e = hipMemcpyAsync(a_f, a_f0, field, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(a_sh, a_sh0, field, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(t_prev, t_nodes, vec, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "copies of the loop");
+    if ((rc = propagate(pl, a_f, a_sh, dk_z, t_mid, 0, pl.p.nz, nullptr, nullptr, st, heat)))
+      return rc;
+    if ((rc = solve_any(th, heat, t_nodes, t_mid, solve_tol, max_iter, ws, nullptr, nullptr, st)))
+      return rc;
+    rc = th.dtype == SHG_C64 ? max_change<float>(th, t_nodes, t_prev, ws, &change, st)
+                             : max_change<double>(th, t_nodes, t_prev, ws, &change, st);
+    if (rc) return rc;
+    ++k;
+    if (change <= tol_t) break;
+  }
+  if (outer_out) *outer_out = k;
+  if (change_out) *change_out = change;
+  return SHG_OK;
+}
+
+}  // namespace shg
+
+using namespace shg;
+
+extern "C" {
+
+int shg_thermal_create(shg_thermal** out, const shg_thermal_params* p, shg_dtype dtype) {
+  if (!out) return fail(SHG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!p) return fail(SHG_EINVAL, "params is NULL");
+  if (dtype != SHG_C64 && dtype != SHG_C128) return fail(SHG_EINVAL, "unknown dtype %d", (int)dtype);
+  int rc = validate_thermal(p);
+  if (rc) return rc;
+  Therm* th = new (std::nothrow) Therm();
+  if (!th) return fail(SHG_ENOMEM, "host allocation failed");
+  th->p = *p;
+  th->dtype = dtype;
+  (void)hipGetDevice(&th->device);
+  build_geom(*th);
+  th->magic = Therm::kMagic;
+  *out = reinterpret_cast<shg_thermal*>(th);
+  return ok();
+}
+
+int shg_thermal_destroy(shg_thermal* t) {
+  if (!t) return ok();
+  int rc = check_therm(t);
+  if (rc) return rc;
+  Therm* th = reinterpret_cast<Therm*>(t);
+  th->magic = 0;
+  delete th;
+  return ok();
+}
+
+size_t shg_thermal_workspace_bytes(const shg_thermal* t) {
+  if (check_therm(t)) return 0;
+  return therm_layout(*reinterpret_cast<const Therm*>(t)).total;
+}
+
+int shg_thermal_solve(shg_thermal* t, const void* heat, void* t_nodes, void* t_mid, double tol,
+                      int32_t max_iter, void* workspace, int32_t* iterations, double* residual,
+                      void* stream) {
+  int rc = check_therm(t);
+  if (rc) return rc;
+  if (!heat || !t_nodes || !workspace)
+    return fail(SHG_EINVAL, "heat, t_nodes and workspace must be non-NULL device pointers");
+  if (!(tol > 0) || max_iter < 1) return fail(SHG_EINVAL, "tol must be > 0 and max_iter >= 1");
+  if ((rc = sticky_device_error())) return rc;
+  Therm* th = reinterpret_cast<Therm*>(t);
+  int it = 0;
+  double res = 0.0;
+  rc = solve_any(*th, heat, t_nodes, t_mid, tol, max_iter, workspace, &it, &res,
+                 (hipStream_t)stream);
+  if (iterations) *iterations = it;
+  if (residual) *residual = res;
+  return rc ? rc : ok();
+}
+
+int shg_self_consistent(shg_plan* plan, shg_thermal* t, const void* a_f0, const void* a_sh0,
+                        const double* dk_z, void* a_f, void* a_sh, void* t_nodes, void* t_mid,
+                        double tol_t, int32_t max_outer, double solve_tol, int32_t max_iter,
+                        void* workspace, int32_t* outer, double* change, void* stream) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if ((rc = check_therm(t))) return rc;
+  Plan* pl = reinterpret_cast<Plan*>(plan);
+  Therm* th = reinterpret_cast<Therm*>(t);
+  if (!a_f0 || !a_sh0 || !a_f || !a_sh || !t_nodes || !t_mid || !workspace)
+    return fail(SHG_EINVAL, "fields, t_nodes, t_mid and workspace must be non-NULL");
+  if (pl->dtype != th->dtype) return fail(SHG_EINVAL, "plan and thermal plan dtypes differ");
+  const shg_thermal_params& q = th->p;
+  if (q.nx != pl->p.nx || q.ny != pl->p.ny || q.nz != pl->p.nz || q.lx != pl->p.lx ||
+      q.ly != pl->p.ly || q.lcr != pl->p.lcr)
+    return fail(SHG_EINVAL, "the thermal grid (nx, ny, nz, lx, ly, lcr) must match the plan's");
+  if (!(tol_t > 0) || max_outer < 1 || !(solve_tol > 0) || max_iter < 1)
+    return fail(SHG_EINVAL, "tolerances must be > 0 and iteration limits >= 1");
+  if ((rc = sticky_device_error())) return rc;
+  int k = 0;
+  double ch = 0.0;
+  rc = self_consistent(*pl, *th, a_f0, a_sh0, dk_z, a_f, a_sh, t_nodes, t_mid, tol_t, max_outer,
+                       solve_tol, max_iter, (char*)workspace, &k, &ch, (hipStream_t)stream);
+  if (outer) *outer = k;
+  if (change) *change = ch;
+  return rc ? rc : ok();
+}
+
+}  // extern "C"

@@ -40,11 +40,13 @@ def test_library_exports_every_declared_symbol(lib):
         assert hasattr(lib, n), n
 
 
-def test_params_struct_layout_matches_c():
-    fields = [f for f, _ in ShgParams._fields_]
+@pytest.mark.parametrize("cstruct,ctype", [("shg_params", ShgParams),
+                                           ("shg_thermal_params", binding.ThermalParams)])
+def test_params_struct_layout_matches_c(cstruct, ctype):
+    fields = [f for f, _ in ctype._fields_]
     prog = ["#include <stdio.h>", "#include <stddef.h>", '#include "shg.h"', "int main(void){",
-            'printf("%zu\\n", sizeof(shg_params));']
-    prog += [f'printf("%zu\\n", offsetof(shg_params, {f}));' for f in fields]
+            f'printf("%zu\\n", sizeof({cstruct}));']
+    prog += [f'printf("%zu\\n", offsetof({cstruct}, {f}));' for f in fields]
     prog += ["return 0;}"]
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "layout.c")
@@ -53,9 +55,9 @@ def test_params_struct_layout_matches_c():
         subprocess.run(["gcc", "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
         out = [int(v) for v in subprocess.run([exe], capture_output=True, text=True,
                                               check=True).stdout.split()]
-    assert out[0] == ctypes.sizeof(ShgParams)
+    assert out[0] == ctypes.sizeof(ctype)
     for f, off in zip(fields, out[1:]):
-        assert getattr(ShgParams, f).offset == off, f
+        assert getattr(ctype, f).offset == off, f
 
 
 def good_params(**kw):
@@ -149,3 +151,47 @@ def test_workload_inputs_are_seeded():
     assert len(batch) == 512 and sizes.count(64) == 128 and sizes.count(256) == 128
     assert all(200 <= x.nz <= 1000 and 0.5 <= x.xi <= 5.0 for x in batch)
     assert [x.nz for x in workloads.c3_batch()] == [x.nz for x in batch]
+
+
+def thermal_create(lib, grid=None, dtype=0, **kw):
+    g = dict(nx=32, ny=16, nz=8, lx=1e-3, ly=1e-3, lcr=5e-3)
+    g.update(grid or {})
+    args = dict(k_th=5.0, h_conv=10.0, t_inf=295.0, t_oven=330.0, faces={"y-": "oven"})
+    args.update(kw)
+    tp = binding.make_thermal_params(g, **args)
+    h = ctypes.c_void_p()
+    rc = lib.shg_thermal_create(ctypes.byref(h), ctypes.byref(tp), dtype)
+    return rc, h, lib.shg_last_error().decode()
+
+
+@pytest.mark.parametrize("bad,needle", [
+    (dict(grid=dict(nx=48)), "power of two"), (dict(grid=dict(nz=0)), "nz"),
+    (dict(grid=dict(lcr=-1.0)), "lcr"), (dict(k_th=0.0), "k_th"), (dict(h_conv=-1.0), "h_conv"),
+    (dict(t_oven=float("nan")), "t_oven"),
+    (dict(faces={}, h_conv=0.0), "not fixed"),
+    (dict(faces={f: "insulated" for f in binding.FACE_NAMES}), "not fixed"),
+])
+def test_thermal_params_rejected(lib, bad, needle):
+    rc, h, msg = thermal_create(lib, **bad)
+    assert rc == binding.SHG_EINVAL and h.value is None and needle in msg
+
+
+def test_thermal_plan_is_host_only_and_sizes_its_workspace(lib):
+    """A thermal plan allocates no device memory, so it is created here; its
+    workspace is seven node vectors plus block partials and scalars."""
+    rc, h, msg = thermal_create(lib)
+    assert rc == binding.SHG_OK, msg
+    n = 32 * 16 * 9
+    vec = (n * 4 + 255) // 256 * 256
+    ws = lib.shg_thermal_workspace_bytes(h)
+    assert 7 * vec < ws < 7 * vec + 64 * 1024
+    rc2, h2, _ = thermal_create(lib, dtype=1)
+    assert lib.shg_thermal_workspace_bytes(h2) > ws
+    assert lib.shg_thermal_destroy(h) == binding.SHG_OK
+    assert lib.shg_thermal_destroy(h2) == binding.SHG_OK
+    # destroyed or foreign handles are refused, not dereferenced as plans
+    junk = (ctypes.c_uint64 * 64)()
+    assert lib.shg_thermal_workspace_bytes(ctypes.cast(junk, ctypes.c_void_p)) == 0
+    it, res = ctypes.c_int32(), ctypes.c_double()
+    assert lib.shg_thermal_solve(ctypes.cast(junk, ctypes.c_void_p), None, None, None, 1e-6, 10,
+                                 None, ctypes.byref(it), ctypes.byref(res), None) == binding.SHG_ESTATE
