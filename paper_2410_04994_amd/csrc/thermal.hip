@@ -21,6 +21,8 @@ struct Therm {
   int device = 0;
   ThermGeom g{};
   int nblk = 0;             // blocks of the grid-stride kernels
+  dim3 dgrid, dblock;       // launch of the tiled direction/apply kernel
+  int nblk_dir = 0;         // its block count
   size_t real_bytes = 4;
 };
 
@@ -39,7 +41,7 @@ static ThermLayout therm_layout(const Therm& th) {
     off += vec;
   }
   L.part = off;
-  off += align256((size_t)th.nblk * 2 * sizeof(double));
+  off += align256((size_t)std::max(2 * th.nblk, th.nblk_dir) * sizeof(double));
   L.sc = off;
   off += align256(16 * sizeof(double));
   L.total = off;
@@ -90,16 +92,39 @@ static void build_geom(Therm& th) {
   g.log2_plane = ilog2((size_t)p.nx * p.ny);
   const double h[3] = {p.lx / p.nx, p.ly / p.ny, p.lcr / p.nz};
   const double beta = p.h_conv / p.k_th;
-  for (int d = 0; d < 3; ++d) g.ih2[d] = 1.0 / (h[d] * h[d]);
-  for (int f = 0; f < 6; ++f) {
-    g.face[f] = p.faces[f];
-    const bool air = p.faces[f] == SHG_FACE_AIR;
-    g.conv[f] = air ? 2.0 * beta / h[f / 2] : 0.0;
-    g.src_conv[f] = air ? 2.0 * beta * (p.t_oven - p.t_inf) / h[f / 2] : 0.0;
+  for (int d = 0; d < 3; ++d) {
+    g.ih2[d] = 1.0 / (h[d] * h[d]);
+    g.conv_lo[d] = p.faces[2 * d] == SHG_FACE_AIR ? 2.0 * beta / h[d] : 0.0;
+    g.conv_hi[d] = p.faces[2 * d + 1] == SHG_FACE_AIR ? 2.0 * beta / h[d] : 0.0;
+  }
+  // per node class: role_d = 0 interior, 1 on the low face, 2 on the high face
+  for (int cls = 0; cls < 27; ++cls) {
+    const int role[3] = {cls % 3, (cls / 3) % 3, cls / 9};
+    bool oven = false;
+    double w = 1.0, dsum = 0.0, src = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      dsum += 2.0 * g.ih2[d];
+      if (role[d] == 0) continue;
+      const int f = 2 * d + (role[d] - 1);
+      w *= 0.5;
+      oven |= p.faces[f] == SHG_FACE_OVEN;
+      if (p.faces[f] == SHG_FACE_AIR) {
+        dsum += 2.0 * beta / h[d];
+        src -= 2.0 * beta * (p.t_oven - p.t_inf) / h[d];
+      }
+    }
+    g.oven[cls] = oven ? 1 : 0;
+    g.w[cls] = oven ? 0.0 : w;
+    g.inv_diag[cls] = oven ? 0.0 : 1.0 / (w * dsum);
+    g.src[cls] = oven ? 0.0 : w * src;
   }
   g.inv_k = 1.0 / p.k_th;
   g.n = (size_t)p.nx * p.ny * (p.nz + 1);
   th.nblk = (int)std::min<size_t>(2048, (g.n + 255) / 256);
+  const int tx = std::min(64, p.nx), ty = 256 / tx;
+  th.dblock = dim3(tx, ty);
+  th.dgrid = dim3(p.nx / tx, p.ny / ty, (g.nzn + kThermZ - 1) / kThermZ);
+  th.nblk_dir = (int)(th.dgrid.x * th.dgrid.y * th.dgrid.z);
   th.real_bytes = th.dtype == SHG_C64 ? 4 : 8;
 }
 
@@ -138,9 +163,9 @@ static int solve_t(Therm& th, const R* heat, R* t_nodes, R* t_mid, double tol, i
   while (it < max_iter && hs[kRz] > 0.0 && bnorm > 0.0) {
     const int chunk = std::min(kCheck, max_iter - it);
     for (int k = 0; k < chunk; ++k) {
-      hipLaunchKernelGGL((th_direction_apply<R>), grid, blk, 0, st, g, (const R*)r, (const R*)pc,
-                         pn, ap, (const double*)sc, part);
-      hipLaunchKernelGGL(th_scalars, dim3(1), blk, 0, st, (const double*)part, th.nblk, 1, sc);
+      hipLaunchKernelGGL((th_direction_apply<R>), th.dgrid, th.dblock, 0, st, g, (const R*)r,
+                         (const R*)pc, pn, ap, (const double*)sc, part);
+      hipLaunchKernelGGL(th_scalars, dim3(1), blk, 0, st, (const double*)part, th.nblk_dir, 1, sc);
       hipLaunchKernelGGL((th_update<R>), grid, blk, 0, st, g, theta, r, (const R*)pn,
                          (const R*)ap, (const double*)sc, part);
       hipLaunchKernelGGL(th_scalars, dim3(1), blk, 0, st, (const double*)part, th.nblk, 2, sc);

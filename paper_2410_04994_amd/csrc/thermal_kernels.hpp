@@ -23,25 +23,24 @@ enum : int { kFaceAir = 0, kFaceOven = 1, kFaceInsulated = 2 };
 struct ThermGeom {
   int nx, ny, nzn;          // nodes per axis (nzn = nz + 1); nx, ny powers of two
   int log2_nx, log2_plane;  // log2(nx), log2(nx ny)
-  int face[6];              // x-, x+, y-, y+, z-, z+
-  double ih2[3];            // 1 / h_d^2
-  double conv[6];           // 2 beta / h_d on each face (0 unless air)
-  double inv_k;             // 1 / k
-  double src_conv[6];       // 2 beta (T_oven - T_inf) / h_d on air faces, else 0
   size_t n;                 // total nodes
+  double inv_k;             // 1 / k
+  // per node class (27 = 3 x 3 x 3: interior / low face / high face per
+  // direction): oven flag, control-volume weight w, 1 / (w diag), and the
+  // boundary source term -w sum_{air faces} 2 beta (T_oven - T_inf) / h
+  double ih2[3];            // 1 / h_d^2
+  double conv_lo[3], conv_hi[3];   // 2 beta / h_d on the low / high face (0 unless air)
+  int oven[27];
+  double w[27], inv_diag[27], src[27];
 };
 
-// Position of node i and its boundary role in each direction.
+// Position of node i: coordinates and class.
 struct NodePos {
   int c[3];                 // x, y, z index
-  bool oven;
+  int cls;                  // sum_d role_d 3^d, role 0 interior, 1 low face, 2 high face
 };
 
-__device__ __forceinline__ bool is_oven(const ThermGeom& g, const int c[3]) {
-  return (c[0] == 0 && g.face[0] == kFaceOven) || (c[0] == g.nx - 1 && g.face[1] == kFaceOven) ||
-         (c[1] == 0 && g.face[2] == kFaceOven) || (c[1] == g.ny - 1 && g.face[3] == kFaceOven) ||
-         (c[2] == 0 && g.face[4] == kFaceOven) || (c[2] == g.nzn - 1 && g.face[5] == kFaceOven);
-}
+__device__ __forceinline__ int role(int c, int n) { return c == 0 ? 1 : (c == n - 1 ? 2 : 0); }
 
 __device__ __forceinline__ NodePos node_pos(const ThermGeom& g, size_t i) {
   NodePos q;
@@ -49,59 +48,40 @@ __device__ __forceinline__ NodePos node_pos(const ThermGeom& g, size_t i) {
   const int r = (int)(i & (((size_t)1 << g.log2_plane) - 1));
   q.c[1] = r >> g.log2_nx;
   q.c[0] = r & (g.nx - 1);
-  q.oven = is_oven(g, q.c);
+  q.cls = role(q.c[0], g.nx) + 3 * role(q.c[1], g.ny) + 9 * role(q.c[2], g.nzn);
   return q;
 }
 
-// The neighbour of q one node along direction d (s = +1 or -1).
-__device__ __forceinline__ NodePos neighbour(const ThermGeom& g, const NodePos& q, int d, int s) {
-  NodePos n = q;
-  n.c[d] += s;
-  n.oven = is_oven(g, n.c);
-  return n;
-}
-
-// Control-volume weight and diagonal of A at a free node.
-__device__ __forceinline__ void node_weight_diag(const ThermGeom& g, const NodePos& q, double* w,
-                                                 double* diag) {
+// Class of the neighbour one node along direction d (s = +1 or -1).
+__device__ __forceinline__ int neighbour_cls(const ThermGeom& g, const NodePos& q, int d, int s) {
   const int nd[3] = {g.nx, g.ny, g.nzn};
-  double ww = 1.0, dg = 0.0;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    dg += 2.0 * g.ih2[d];
-    if (q.c[d] == 0) {
-      ww *= 0.5;
-      dg += g.conv[2 * d];
-    } else if (q.c[d] == nd[d] - 1) {
-      ww *= 0.5;
-      dg += g.conv[2 * d + 1];
-    }
-  }
-  *w = ww;
-  *diag = ww * dg;
+  const int p3[3] = {1, 3, 9};
+  const int before = role(q.c[d], nd[d]);
+  const int after = role(q.c[d] + s, nd[d]);
+  return q.cls + (after - before) * p3[d];
 }
 
-// (A v)_i at a free node; v(j, qj) gives the value at node j with position qj.
-template <typename V>
-__device__ __forceinline__ double apply_node(const ThermGeom& g, const NodePos& q, size_t i, V v,
-                                             double w) {
+// (A v)_i at a free node; v(j, cls_j) gives the value at node j of class cls_j.
+// Arithmetic in R (the solver's storage precision).
+template <typename R, typename V>
+__device__ __forceinline__ R apply_node(const ThermGeom& g, const NodePos& q, size_t i, V v) {
   const int nd[3] = {g.nx, g.ny, g.nzn};
   const size_t st[3] = {1, (size_t)g.nx, (size_t)g.nx * g.ny};
-  const double c = v(i, q);
-  double acc = 0.0;
+  const R c = v(i, q.cls);
+  R acc = (R)0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
+    const R ih2 = (R)g.ih2[d];
     if (q.c[d] == 0) {
-      acc += (2.0 * c - 2.0 * v(i + st[d], neighbour(g, q, d, 1))) * g.ih2[d] + g.conv[2 * d] * c;
+      acc += (c - v(i + st[d], neighbour_cls(g, q, d, 1))) * ((R)2 * ih2) + (R)g.conv_lo[d] * c;
     } else if (q.c[d] == nd[d] - 1) {
-      acc += (2.0 * c - 2.0 * v(i - st[d], neighbour(g, q, d, -1))) * g.ih2[d] +
-             g.conv[2 * d + 1] * c;
+      acc += (c - v(i - st[d], neighbour_cls(g, q, d, -1))) * ((R)2 * ih2) + (R)g.conv_hi[d] * c;
     } else {
-      acc += (2.0 * c - v(i + st[d], neighbour(g, q, d, 1)) - v(i - st[d], neighbour(g, q, d, -1))) *
-             g.ih2[d];
+      acc += ((R)2 * c - v(i + st[d], neighbour_cls(g, q, d, 1)) -
+              v(i - st[d], neighbour_cls(g, q, d, -1))) * ih2;
     }
   }
-  return w * acc;
+  return (R)g.w[q.cls] * acc;
 }
 
 // Fixed-order sum of one double per thread over a 256-thread block; the result
@@ -137,7 +117,7 @@ __global__ void __launch_bounds__(256) th_init(ThermGeom g, const R* __restrict_
                                                R* __restrict__ theta, R* __restrict__ p0) {
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < g.n; i += (size_t)gridDim.x * 256) {
     const NodePos q = node_pos(g, i);
-    theta[i] = q.oven ? (R)0 : (R)((double)t_in[i] - t_oven);
+    theta[i] = g.oven[q.cls] ? (R)0 : (R)((double)t_in[i] - t_oven);
     p0[i] = (R)0;
   }
 }
@@ -151,24 +131,15 @@ __global__ void __launch_bounds__(256) th_residual(ThermGeom g, const R* __restr
   double rz = 0.0, bb = 0.0;
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < g.n; i += (size_t)gridDim.x * 256) {
     const NodePos q = node_pos(g, i);
-    if (q.oven) {
+    if (g.oven[q.cls]) {
       r[i] = (R)0;
       continue;
     }
-    double w, dg;
-    node_weight_diag(g, q, &w, &dg);
-    double src = (double)heat[i] * g.inv_k;
-    const int nd[3] = {g.nx, g.ny, g.nzn};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      if (q.c[d] == 0) src -= g.src_conv[2 * d];
-      else if (q.c[d] == nd[d] - 1) src -= g.src_conv[2 * d + 1];
-    }
-    const double b = w * src;
-    const double ax = apply_node(g, q, i, [&](size_t j, const NodePos&) { return (double)theta[j]; }, w);
-    const double rr = b - ax;
-    r[i] = (R)rr;
-    rz += (double)(R)rr * ((double)(R)rr / dg);
+    const double b = g.w[q.cls] * ((double)heat[i] * g.inv_k) + g.src[q.cls];
+    const double ax = (double)apply_node<R>(g, q, i, [&](size_t j, int) { return theta[j]; });
+    const R rr = (R)(b - ax);
+    r[i] = rr;
+    rz += (double)rr * (double)rr * g.inv_diag[q.cls];
     bb += b * b;
   }
   rz = block_sum256(rz, red);
@@ -179,41 +150,86 @@ __global__ void __launch_bounds__(256) th_residual(ThermGeom g, const R* __restr
   }
 }
 
-// p_new = r / diag + beta p_old at the node and its neighbours; Ap = A p_new;
-// per-block partials of p_new . Ap.
+// Class of the node at (x, y, z).
+__device__ __forceinline__ int node_cls(const ThermGeom& g, int x, int y, int z) {
+  return role(x, g.nx) + 3 * role(y, g.ny) + 9 * role(z, g.nzn);
+}
+
+// p_new = r / diag + beta p_old; Ap = A p_new; per-block partials of p_new . Ap.
+// 2.5-D tiling: a block of TX x TY threads owns an x-y tile and marches through
+// kThermZ planes.  The direction of the planes below and above stays in
+// registers; x and y neighbours come from an LDS copy of the current plane with
+// a one-node halo.  r and p_old are read about once per node (plus the halo).
+// p_new vanishes on oven nodes because r and p_old do and 1/diag is 0 there.
+constexpr int kThermZ = 16;
+
 template <typename R>
 __global__ void __launch_bounds__(256) th_direction_apply(ThermGeom g, const R* __restrict__ r,
                                                           const R* __restrict__ p_old,
                                                           R* __restrict__ p_new, R* __restrict__ ap,
                                                           const double* __restrict__ sc,
                                                           double* __restrict__ part) {
+  __shared__ R tile[420];        // (TY + 2) x (TX + 2) <= 420 for TX TY = 256, TX in [16, 64]
   __shared__ double red[4];
-  const double beta = sc[kBeta];
+  const int TX = blockDim.x, TY = blockDim.y;
+  const int LW = TX + 2;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int x = blockIdx.x * TX + tx, y = blockIdx.y * TY + ty;
+  const int z0 = blockIdx.z * kThermZ, z1 = min(z0 + kThermZ, g.nzn);
+  const size_t plane = (size_t)g.nx * g.ny;
+  const R beta = (R)sc[kBeta];
+  auto pdir = [&](int xx, int yy, int zz) -> R {
+    const size_t j = (size_t)zz * plane + (size_t)yy * g.nx + xx;
+    return r[j] * (R)g.inv_diag[node_cls(g, xx, yy, zz)] + beta * p_old[j];
+  };
+  const R ih2x = (R)g.ih2[0], ih2y = (R)g.ih2[1], ih2z = (R)g.ih2[2];
+  R pm = z0 > 0 ? pdir(x, y, z0 - 1) : (R)0;
+  R pc = pdir(x, y, z0);
   double pap = 0.0;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < g.n; i += (size_t)gridDim.x * 256) {
-    const NodePos q = node_pos(g, i);
-    if (q.oven) {
-      p_new[i] = (R)0;
-      ap[i] = (R)0;
-      continue;
+  for (int z = z0; z < z1; ++z) {
+    const R pn = z + 1 < g.nzn ? pdir(x, y, z + 1) : (R)0;
+    // plane z into LDS with its x / y halo (outside the grid: unused)
+    tile[(ty + 1) * LW + tx + 1] = pc;
+    if (tx == 0) tile[(ty + 1) * LW] = x > 0 ? pdir(x - 1, y, z) : (R)0;
+    if (tx == TX - 1) tile[(ty + 1) * LW + TX + 1] = x + 1 < g.nx ? pdir(x + 1, y, z) : (R)0;
+    if (ty == 0) tile[tx + 1] = y > 0 ? pdir(x, y - 1, z) : (R)0;
+    if (ty == TY - 1) tile[(TY + 1) * LW + tx + 1] = y + 1 < g.ny ? pdir(x, y + 1, z) : (R)0;
+    __syncthreads();
+    const int cls = node_cls(g, x, y, z);
+    const size_t i = (size_t)z * plane + (size_t)y * g.nx + x;
+    R a = (R)0;
+    if (!g.oven[cls]) {
+      const R xm = tile[(ty + 1) * LW + tx], xp = tile[(ty + 1) * LW + tx + 2];
+      const R ym = tile[ty * LW + tx + 1], yp = tile[(ty + 2) * LW + tx + 1];
+      R acc;
+      if (x == 0) acc = (pc - xp) * ((R)2 * ih2x) + (R)g.conv_lo[0] * pc;
+      else if (x == g.nx - 1) acc = (pc - xm) * ((R)2 * ih2x) + (R)g.conv_hi[0] * pc;
+      else acc = ((R)2 * pc - xp - xm) * ih2x;
+      if (y == 0) acc += (pc - yp) * ((R)2 * ih2y) + (R)g.conv_lo[1] * pc;
+      else if (y == g.ny - 1) acc += (pc - ym) * ((R)2 * ih2y) + (R)g.conv_hi[1] * pc;
+      else acc += ((R)2 * pc - yp - ym) * ih2y;
+      if (z == 0) acc += (pc - pn) * ((R)2 * ih2z) + (R)g.conv_lo[2] * pc;
+      else if (z == g.nzn - 1) acc += (pc - pm) * ((R)2 * ih2z) + (R)g.conv_hi[2] * pc;
+      else acc += ((R)2 * pc - pn - pm) * ih2z;
+      a = (R)g.w[cls] * acc;
+      pap += (double)pc * (double)a;
     }
-    // direction at node j, rounded to R as it is stored
-    auto pdir = [&](size_t j, const NodePos& qj) {
-      if (qj.oven) return 0.0;
-      double wj, dj;
-      node_weight_diag(g, qj, &wj, &dj);
-      return (double)(R)((double)r[j] / dj + beta * (double)p_old[j]);
-    };
-    double w, dg;
-    node_weight_diag(g, q, &w, &dg);
-    const double pc = pdir(i, q);
-    const double a = apply_node(g, q, i, pdir, w);
-    p_new[i] = (R)pc;
-    ap[i] = (R)a;
-    pap += pc * (double)(R)a;
+    p_new[i] = pc;
+    ap[i] = a;
+    __syncthreads();   // the tile is rewritten for the next plane
+    pm = pc;
+    pc = pn;
   }
-  pap = block_sum256(pap, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = pap;
+  const int flat = ty * TX + tx;
+  // block_sum256 indexes threads by threadIdx.x; use the flat index instead
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) pap += __shfl_down(pap, off, 64);
+  if ((flat & 63) == 0) red[flat >> 6] = pap;
+  __syncthreads();
+  if (flat == 0) {
+    const size_t b = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    part[b] = red[0] + red[1] + red[2] + red[3];
+  }
 }
 
 // theta += alpha p; r -= alpha Ap; partials of r.z and r.r.
@@ -223,17 +239,15 @@ __global__ void __launch_bounds__(256) th_update(ThermGeom g, R* __restrict__ th
                                                  const double* __restrict__ sc,
                                                  double* __restrict__ part) {
   __shared__ double red[4];
-  const double alpha = sc[kAlpha];
+  const R alpha = (R)sc[kAlpha];
   double rz = 0.0, rr = 0.0;
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < g.n; i += (size_t)gridDim.x * 256) {
     const NodePos q = node_pos(g, i);
-    if (q.oven) continue;
-    double w, dg;
-    node_weight_diag(g, q, &w, &dg);
-    theta[i] = (R)((double)theta[i] + alpha * (double)p[i]);
-    const R rn = (R)((double)r[i] - alpha * (double)ap[i]);
+    if (g.oven[q.cls]) continue;
+    theta[i] = theta[i] + alpha * p[i];
+    const R rn = r[i] - alpha * ap[i];
     r[i] = rn;
-    rz += (double)rn * ((double)rn / dg);
+    rz += (double)rn * (double)rn * g.inv_diag[q.cls];
     rr += (double)rn * (double)rn;
   }
   rz = block_sum256(rz, red);
