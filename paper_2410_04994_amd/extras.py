@@ -1,6 +1,8 @@
 """Secondary benchmark lines reported beside the single-instance forward march:
-the batched sweep (512 instances, sizes 64/128/256 in 1:2:1, nz in [200, 1000])
-and forward + adjoint on the 256 x 256 x 1000 differentiation workload."""
+the batched sweep (512 instances, sizes 64/128/256 in 1:2:1, nz in [200, 1000]),
+forward + adjoint on the 256 x 256 x 1000 differentiation workload, the heat
+equation for the heat of the 256 x 256 x 1000 march, and the self-consistent
+field <-> temperature loop of the 50 W workload at 256 x 256 x 1000."""
 from __future__ import annotations
 
 import time
@@ -69,9 +71,70 @@ def fwd_adj(device, reps=2):
             "frac_hbm_at_224B": round(wl.cell_steps / sec * 224 / 8e12, 4)}
 
 
+def thermal(device):
+    """Heat equation (open-top oven) for the heat source of the benchmark march:
+    cold start to a relative residual of 1e-6.  Convention: 40 B per node and
+    iteration (direction/stencil pass 16 B, update pass 24 B)."""
+    import torch
+    import workloads
+    from paper_2410_04994_amd import Plan, Thermal, beams, autotune
+    wl = workloads.c2_plain_c64()
+    plan = Plan(wl.params(), "c64")
+    autotune.tune_single(plan)
+    theta = torch.from_numpy(workloads.phase_noise(wl)).to(device)
+    a = beams.pump_for(wl, theta=theta, dtype=torch.complex64, device=device)
+    b = torch.zeros_like(a)
+    heat, _ = plan.propagate_heat(a, b)
+    th = Thermal(wl.params(), dtype="c64", **workloads.open_top_oven())
+    th.workspace(device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t, _, iters, res = th.solve(heat, tol=1e-6, max_iter=40000)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    nodes = wl.nx * wl.ny * (wl.nz + 1)
+    return {"workload": f"heat_equation_{wl.nx}x{wl.ny}x{wl.nz + 1}_open_top_oven",
+            "nodes": nodes, "iterations": iters, "residual": res, "ms": round(sec * 1e3, 2),
+            "node_iterations_per_s": round(nodes * iters / sec, 1),
+            "frac_hbm_at_40B": round(nodes * iters / sec * 40 / 8e12, 4),
+            "t_max_rise_K": round(float(t.max()) - workloads.T_OVEN, 4)}
+
+
+def self_consistent_loop(device):
+    """Self-consistent loop of the 50 W temperature-field workload (dk(T), thermal
+    lens) at 256 x 256 x 1000 on the same physical window: until the largest
+    change of T is below 1 mK."""
+    import torch
+    import workloads
+    from paper_2410_04994_amd import Plan, Thermal, beams, autotune, self_consistent
+    base = workloads.c5_thermal_c64()
+    wl = base.with_(name="c5_thermal_256x256x1000", nx=256, ny=256, nz=1000)
+    plan = Plan(wl.params(), "c64")
+    autotune.tune_single(plan)
+    a0 = beams.pump_for(wl, dtype=torch.complex64, device=device)
+    b0 = torch.zeros_like(a0)
+    th = Thermal(wl.params(), dtype="c64", **workloads.open_top_oven())
+    th.workspace(device)
+    # the same march at the uniform oven temperature, for comparison
+    a_u, b_u = a0.clone(), b0.clone()
+    p_u = plan.propagate(a_u, b_u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = self_consistent(plan, th, a0, b0, tol_t=1e-3, max_outer=20, solve_tol=1e-6,
+                          max_iter=40000)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    # exit powers of a march at the converged temperature field
+    p_sc = plan.propagate(a0.clone(), b0.clone(), temp=out["t_mid"])
+    return {"workload": wl.name, "marches": out["outer"], "last_change_K": out["change"],
+            "ms": round(sec * 1e3, 1), "t_max_rise_K": round(float(out["t_nodes"].max()) - workloads.T_OVEN, 4),
+            "p_sh_uniform_oven_W": round(float(p_u[1]), 5), "p_sh_self_consistent_W": round(float(p_sc[1]), 5)}
+
+
 def run_all(device) -> dict:
     out = {}
-    for name, fn in (("batched", batched), ("fwd_adj", fwd_adj)):
+    for name, fn in (("batched", batched), ("fwd_adj", fwd_adj), ("thermal", thermal),
+                     ("self_consistent", self_consistent_loop)):
         try:
             out[name] = fn(device)
         except Exception as exc:

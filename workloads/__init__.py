@@ -173,6 +173,14 @@ def c5_thermal_c64() -> Workload:
                  extra={"t0": T_OVEN, "dT_peak": 3.0, "wT_over_w0": 1.5})
 
 
+def open_top_oven() -> dict:
+    """Thermal set-up of the paper's experiment (Sec. 2: the crystal's base on an
+    oven at T_oven, the other faces in ambient air).  The paper gives neither
+    the conductivity nor the convection coefficient; these are stand-ins of the
+    right order for MgO:sPPLT in still air."""
+    return dict(k_th=8.4, h_conv=10.0, t_inf=298.15, t_oven=T_OVEN, faces={"y-": "oven"})
+
+
 def c3_batch(n_instances: int = 512, seed: int = 3) -> List[Workload]:
     """Batched sweep: sizes 64/128/256 in the ratio 1:2:1 (shuffled), per-instance
     nz ~ U{200..1000}, xi ~ U[0.5, 5], detuning ~ U[-2, 2] K mapped to
