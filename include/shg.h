@@ -226,10 +226,10 @@ const char *shg_last_error(void);
  * faces obey -k dT/dn = h_conv (T - t_inf); insulated faces have no flux.
  * Every other node obeys the second-order 7-point equation, with the outside
  * neighbour of a face node removed through the central difference of its
- * boundary condition.  The solver is Jacobi-preconditioned conjugate
- * gradients on the control-volume (symmetric) form of those equations, in the
- * plan's real type with FP64 reductions; it synchronises the stream to test
- * convergence, so it cannot be captured into a graph.
+ * boundary condition.  Both solvers (below) work on the control-volume
+ * (symmetric) form of those equations and synchronise the stream (set-up,
+ * convergence tests, the residual report), so they cannot be captured into a
+ * graph.
  * Temperatures are arrays in the plan's real type: t_nodes [nz + 1][ny][nx]
  * and the mid-planes t_mid [nz][ny][nx] = (T_l + T_{l+1}) / 2 that
  * shg_propagate takes as its temperature field. */
@@ -237,10 +237,19 @@ typedef struct shg_thermal shg_thermal;
 
 enum { SHG_FACE_AIR = 0, SHG_FACE_OVEN = 1, SHG_FACE_INSULATED = 2 };
 
+/* Solvers.  SHG_THERMAL_DIRECT: fast diagonalisation.  Divided by the
+ * control-volume weights, the operator is the Kronecker sum of three 1-D
+ * operators (constant k, oven faces are whole planes), so T follows exactly
+ * from their eigendecompositions (rocSOLVER, once per plan, FP64) and six FP64
+ * GEMM mode products (rocBLAS) per solve; tol and max_iter are ignored and
+ * iterations is 0.  SHG_THERMAL_CG: Jacobi-preconditioned conjugate gradients
+ * in the plan's real type with FP64 reductions, stopped at |r| <= tol |b|. */
+enum { SHG_THERMAL_DIRECT = 0, SHG_THERMAL_CG = 1 };
+
 typedef struct {
   int32_t nx, ny, nz;     /* the field grid; nodes nx x ny x (nz + 1)          */
   int32_t faces[6];       /* x-, x+, y-, y+, z-, z+: SHG_FACE_*                 */
-  int32_t reserved;       /* 0                                                  */
+  int32_t method;         /* SHG_THERMAL_DIRECT (default) or SHG_THERMAL_CG    */
   double lx, ly, lcr;     /* as in shg_params [m]                               */
   double k_th;            /* thermal conductivity [W/(m K)]                     */
   double h_conv;          /* convection coefficient of air faces [W/(m^2 K)]    */
@@ -256,7 +265,10 @@ int shg_thermal_create(shg_thermal **out, const shg_thermal_params *p, shg_dtype
 int shg_thermal_destroy(shg_thermal *th);
 
 /* Device workspace of shg_thermal_solve and shg_self_consistent: seven node
- * vectors (nx ny (nz + 1) reals each) plus a few KB. */
+ * vectors (nx ny (nz + 1) reals each), two FP64 node vectors for the direct
+ * solver, and a few KB.  The direct solver also keeps its factors (3 m^2 + 3 m
+ * doubles per axis, m <= nz + 1) in device memory owned by the plan, built on
+ * its first solve. */
 size_t shg_thermal_workspace_bytes(const shg_thermal *th);
 
 /* Solve for T with source heat [nz + 1][ny][nx] [W/m^3].
@@ -264,9 +276,13 @@ size_t shg_thermal_workspace_bytes(const shg_thermal *th);
  *   t_mid      out: mid-plane temperatures, or NULL
  *   tol        stop when |r| <= tol |b| (2-norms of the weighted system)
  *   iterations, residual  out (host pointers, may be NULL)
+ * residual: the direct solver reports |b - A theta| / |b| of its FP64
+ * solution (before T is rounded to the plan's precision); CG reports the
+ * relative norm of its recursively updated residual.
  * Returns after the solve (the host waits on the stream).  Errors:
  * SHG_ESTATE, SHG_EINVAL (NULL arrays or workspace, tol <= 0, max_iter < 1),
- * SHG_EDEVICE (including a diverged iteration). */
+ * SHG_ENOMEM, SHG_EDEVICE (including a diverged iteration or a failed
+ * eigensolver). */
 int shg_thermal_solve(shg_thermal *th, const void *heat, void *t_nodes, void *t_mid, double tol,
                       int32_t max_iter, void *workspace, int32_t *iterations, double *residual,
                       void *stream);

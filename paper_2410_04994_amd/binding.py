@@ -47,7 +47,7 @@ FACE_KINDS = {"air": SHG_FACE_AIR, "oven": SHG_FACE_OVEN, "insulated": SHG_FACE_
 
 class ThermalParams(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-                ("faces", ctypes.c_int32 * 6), ("reserved", ctypes.c_int32),
+                ("faces", ctypes.c_int32 * 6), ("method", ctypes.c_int32),
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lcr", ctypes.c_double),
                 ("k_th", ctypes.c_double), ("h_conv", ctypes.c_double), ("t_inf", ctypes.c_double),
                 ("t_oven", ctypes.c_double)]
@@ -312,14 +312,18 @@ def propagate_batch(plans: Sequence[Plan], a_f: Sequence, a_sh: Sequence, dk_z: 
     return powers
 
 
+THERMAL_METHODS = {"direct": 0, "cg": 1}
+
+
 def make_thermal_params(params: dict, k_th: float, h_conv: float, t_inf: float, t_oven: float,
-                        faces: dict) -> ThermalParams:
-    """faces: face name ("x-" .. "z+") -> "oven" | "air" | "insulated" (default air)."""
+                        faces: dict, method: str = "direct") -> ThermalParams:
+    """faces: face name ("x-" .. "z+") -> "oven" | "air" | "insulated" (default air);
+    method: "direct" (fast diagonalisation) or "cg"."""
     tp = ThermalParams()
     tp.nx, tp.ny, tp.nz = int(params["nx"]), int(params["ny"]), int(params["nz"])
     for i, f in enumerate(FACE_NAMES):
         tp.faces[i] = FACE_KINDS[faces.get(f, "air")]
-    tp.reserved = 0
+    tp.method = THERMAL_METHODS[method]
     tp.lx, tp.ly, tp.lcr = params["lx"], params["ly"], params["lcr"]
     tp.k_th, tp.h_conv, tp.t_inf, tp.t_oven = k_th, h_conv, t_inf, t_oven
     return tp
@@ -329,12 +333,13 @@ class Thermal:
     """Owns an shg_thermal: the heat-equation solver on the nodes of a field grid."""
 
     def __init__(self, params: dict, k_th: float, h_conv: float, t_inf: float, t_oven: float,
-                 faces: dict, dtype: str = "c64"):
+                 faces: dict, dtype: str = "c64", method: str = "direct"):
         lib = load_library()
         self.params = dict(params)
         self.dtype = dtype
+        self.method = method
         self.t_oven = t_oven
-        self._cp = make_thermal_params(params, k_th, h_conv, t_inf, t_oven, faces)
+        self._cp = make_thermal_params(params, k_th, h_conv, t_inf, t_oven, faces, method)
         h = _VP()
         _check(lib.shg_thermal_create(ctypes.byref(h), ctypes.byref(self._cp),
                                       SHG_C64 if dtype == "c64" else SHG_C128))

@@ -1,17 +1,31 @@
 // Heat equation and the self-consistent field <-> temperature loop: thermal
-// plans, the Jacobi-preconditioned conjugate-gradient driver and the loop of
-// the flowchart in Sec. 4 (q = 0 -> T -> march with dk(T) -> q -> T -> ...).
+// plans, the two solvers (fast diagonalisation with FP64 GEMMs, the default;
+// Jacobi-preconditioned conjugate gradients) and the loop of the flowchart in
+// Sec. 4 (q = 0 -> T -> march with dk(T) -> q -> T -> ...).
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "plan.hpp"
 #include "thermal_kernels.hpp"
 
 namespace shg {
+
+// Device state of the direct solver, built on its first use.
+struct Fdm {
+  bool ready = false;
+  rocblas_handle h = nullptr;
+  FdmBox box{};
+  double* pm[3] = {};       // forward factors P_d (column-major m_d x m_d)
+  double* qm[3] = {};       // backward factors Q_d
+  double* lam[3] = {};      // eigenvalues
+};
 
 struct Therm {
   static constexpr uint64_t kMagic = 0x5348475f54484552ull;  // "SHG_THER"
@@ -24,12 +38,13 @@ struct Therm {
   dim3 dgrid, dblock;       // launch of the tiled direction/apply kernel
   int nblk_dir = 0;         // its block count
   size_t real_bytes = 4;
+  Fdm fdm;
 };
 
 // Workspace: theta, r, p0, p1, Ap, t_prev, heat (one node vector each), block
 // partials, device scalars.
 struct ThermLayout {
-  size_t theta, r, p0, p1, ap, t_prev, heat, part, sc, total;
+  size_t theta, r, p0, p1, ap, t_prev, heat, part, sc, f0, f1, total;
 };
 
 static ThermLayout therm_layout(const Therm& th) {
@@ -44,6 +59,12 @@ static ThermLayout therm_layout(const Therm& th) {
   off += align256((size_t)std::max(2 * th.nblk, th.nblk_dir) * sizeof(double));
   L.sc = off;
   off += align256(16 * sizeof(double));
+  L.f0 = L.f1 = off;
+  if (th.p.method == SHG_THERMAL_DIRECT) {
+    const size_t fb = align256(th.g.n * sizeof(double));
+    L.f1 = off + fb;
+    off += 2 * fb;
+  }
   L.total = off;
   return L;
 }
@@ -73,6 +94,8 @@ static int validate_thermal(const shg_thermal_params* p) {
   }
   if (!oven && !cooled)
     return fail(SHG_EINVAL, "no oven face and no convective face: the temperature is not fixed");
+  if (p->method != SHG_THERMAL_DIRECT && p->method != SHG_THERMAL_CG)
+    return fail(SHG_EINVAL, "method=%d is not SHG_THERMAL_DIRECT or SHG_THERMAL_CG", p->method);
   return SHG_OK;
 }
 
@@ -198,8 +221,192 @@ static int solve_t(Therm& th, const R* heat, R* t_nodes, R* t_mid, double tol, i
   return SHG_OK;
 }
 
+static void free_fdm(Fdm& f) {
+  for (int d = 0; d < 3; ++d) {
+    if (f.pm[d]) (void)hipFree(f.pm[d]);
+    if (f.qm[d]) (void)hipFree(f.qm[d]);
+    if (f.lam[d]) (void)hipFree(f.lam[d]);
+    f.pm[d] = f.qm[d] = f.lam[d] = nullptr;
+  }
+  if (f.h) (void)rocblas_destroy_handle(f.h);
+  f.h = nullptr;
+  f.ready = false;
+}
+
+static int blas_fail(rocblas_status s, const char* what) {
+  return fail(SHG_EDEVICE, "%s: %s", what, rocblas_status_to_string(s));
+}
+
+// The 1-D operators, their eigendecompositions (rocSOLVER, tridiagonal divide
+// and conquer, FP64) and the factors P_d, Q_d.
+static int fdm_setup(Therm& th, hipStream_t st) {
+  Fdm& f = th.fdm;
+  if (f.ready) return SHG_OK;
+  free_fdm(f);
+  rocblas_status bs = rocblas_create_handle(&f.h);
+  if (bs != rocblas_status_success) return blas_fail(bs, "rocblas_create_handle");
+  bs = rocblas_set_stream(f.h, st);
+  if (bs != rocblas_status_success) return blas_fail(bs, "rocblas_set_stream");
+  const shg_thermal_params& p = th.p;
+  const int nd[3] = {p.nx, p.ny, p.nz + 1};
+  const double h[3] = {p.lx / p.nx, p.ly / p.ny, p.lcr / p.nz};
+  const double beta = p.h_conv / p.k_th;
+  double *dd = nullptr, *ee = nullptr, *uu = nullptr, *ww = nullptr;
+  rocblas_int* info = nullptr;
+  int rc = SHG_OK;
+  hipError_t e = hipSuccess;
+  for (int d = 0; d < 3 && rc == SHG_OK; ++d) {
+    const int lo = p.faces[2 * d], hi = p.faces[2 * d + 1];
+    const int a = lo == SHG_FACE_OVEN ? 1 : 0;
+    const int b = nd[d] - 1 - (hi == SHG_FACE_OVEN ? 1 : 0);
+    const int m = b - a + 1;
+    f.box.a[d] = a;
+    f.box.m[d] = m;
+    const double ih2 = 1.0 / (h[d] * h[d]);
+    const double clo = lo == SHG_FACE_AIR ? 2.0 * beta / h[d] : 0.0;
+    const double chi = hi == SHG_FACE_AIR ? 2.0 * beta / h[d] : 0.0;
+    // weighted symmetric operator S and weights on the free nodes a..b
+    std::vector<double> w(m), sd(m), D(m), E(std::max(m - 1, 1));
+    for (int k = 0; k < m; ++k) {
+      const int i = a + k;
+      if (i == 0) {
+        w[k] = 0.5;
+        sd[k] = ih2 + 0.5 * clo;
+      } else if (i == nd[d] - 1) {
+        w[k] = 0.5;
+        sd[k] = ih2 + 0.5 * chi;
+      } else {
+        w[k] = 1.0;
+        sd[k] = 2.0 * ih2;
+      }
+    }
+    for (int k = 0; k < m; ++k) D[k] = sd[k] / w[k];
+    for (int k = 0; k + 1 < m; ++k) E[k] = -ih2 / std::sqrt(w[k] * w[k + 1]);
+    const size_t mm = (size_t)m * m;
+    e = hipMalloc(&dd, m * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&ee, E.size() * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&uu, mm * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&ww, m * sizeof(double));
+    if (e == hipSuccess && !info) e = hipMalloc(&info, sizeof(rocblas_int));
+    if (e == hipSuccess) e = hipMalloc(&f.pm[d], mm * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&f.qm[d], mm * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&f.lam[d], m * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpyAsync(dd, D.data(), m * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(ee, E.data(), E.size() * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(ww, w.data(), m * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "direct solver set-up");
+    } else {
+      bs = rocsolver_dstedc(f.h, rocblas_evect_tridiagonal, m, dd, ee, uu, m, info);
+      rocblas_int hinfo = 0;
+      if (bs == rocblas_status_success)
+        e = hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (bs != rocblas_status_success) {
+        rc = blas_fail(bs, "rocsolver_dstedc");
+      } else if (e != hipSuccess) {
+        rc = hip_fail(e, "rocsolver_dstedc");
+      } else if (hinfo != 0) {
+        rc = fail(SHG_EDEVICE, "tridiagonal eigensolver failed (info %d)", (int)hinfo);
+      } else {
+        hipLaunchKernelGGL(fdm_factors, dim3((unsigned)std::min<size_t>(4096, (mm + 255) / 256)),
+                           dim3(256), 0, st, m, (const double*)uu, (const double*)ww, f.pm[d],
+                           f.qm[d]);
+        e = hipMemcpyAsync(f.lam[d], dd, m * sizeof(double), hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = hip_fail(e, "direct solver factors");
+      }
+    }
+    for (double** q : {&dd, &ee, &uu, &ww}) {
+      if (*q) (void)hipFree(*q);
+      *q = nullptr;
+    }
+  }
+  if (info) (void)hipFree(info);
+  if (rc) {
+    free_fdm(f);
+    return rc;
+  }
+  f.ready = true;
+  return SHG_OK;
+}
+
+// y = M along one axis of the packed m0 x m1 x m2 array x (x fastest).
+static int fdm_mode(Fdm& f, int axis, const double* mat, const double* x, double* y) {
+  const int m0 = f.box.m[0], m1 = f.box.m[1], m2 = f.box.m[2];
+  const double one = 1.0, zero = 0.0;
+  rocblas_status bs;
+  if (axis == 0) {
+    bs = rocblas_dgemm(f.h, rocblas_operation_none, rocblas_operation_none, m0, m1 * m2, m0, &one,
+                       mat, m0, x, m0, &zero, y, m0);
+  } else if (axis == 1) {
+    bs = rocblas_dgemm_strided_batched(f.h, rocblas_operation_none, rocblas_operation_transpose, m0,
+                                       m1, m1, &one, x, m0, (rocblas_stride)m0 * m1, mat, m1, 0,
+                                       &zero, y, m0, (rocblas_stride)m0 * m1, m2);
+  } else {
+    bs = rocblas_dgemm(f.h, rocblas_operation_none, rocblas_operation_transpose, m0 * m1, m2, m2,
+                       &one, x, m0 * m1, mat, m2, &zero, y, m0 * m1);
+  }
+  return bs == rocblas_status_success ? SHG_OK : blas_fail(bs, "rocblas_dgemm");
+}
+
+template <typename R>
+static int solve_direct(Therm& th, const R* heat, R* t_nodes, R* t_mid, char* ws, double* resid_out,
+                        hipStream_t st) {
+  int rc = fdm_setup(th, st);
+  if (rc) return rc;
+  Fdm& f = th.fdm;
+  rocblas_status bs = rocblas_set_stream(f.h, st);
+  if (bs != rocblas_status_success) return blas_fail(bs, "rocblas_set_stream");
+  const ThermLayout L = therm_layout(th);
+  const ThermGeom& g = th.g;
+  double* f0 = (double*)(ws + L.f0);
+  double* f1 = (double*)(ws + L.f1);
+  double* part = (double*)(ws + L.part);
+  double* sc = (double*)(ws + L.sc);
+  const size_t np = (size_t)f.box.m[0] * f.box.m[1] * f.box.m[2];
+  const dim3 grid((unsigned)std::min<size_t>(4096, (np + 255) / 256)), blk(256);
+  hipLaunchKernelGGL((fdm_gather<R>), grid, blk, 0, st, g, f.box, heat, f0);
+  // forward transforms x, y, z; divide; backward transforms
+  if ((rc = fdm_mode(f, 0, f.pm[0], f0, f1)) || (rc = fdm_mode(f, 1, f.pm[1], f1, f0)) ||
+      (rc = fdm_mode(f, 2, f.pm[2], f0, f1)))
+    return rc;
+  hipLaunchKernelGGL(fdm_divide, grid, blk, 0, st, f.box, (const double*)f.lam[0],
+                     (const double*)f.lam[1], (const double*)f.lam[2], f1);
+  if ((rc = fdm_mode(f, 0, f.qm[0], f1, f0)) || (rc = fdm_mode(f, 1, f.qm[1], f0, f1)) ||
+      (rc = fdm_mode(f, 2, f.qm[2], f1, f0)))
+    return rc;
+  // f1 <- theta in FP64 on all nodes (the packed solution in f0 is then free)
+  hipLaunchKernelGGL((fdm_scatter<R>), dim3(th.nblk), blk, 0, st, g, f.box, (const double*)f0,
+                     th.p.t_oven, f1, t_nodes);
+  if (t_mid) {
+    const size_t plane = (size_t)g.nx * g.ny;
+    hipLaunchKernelGGL((th_midplanes<R>), dim3(th.nblk), blk, 0, st, (const R*)t_nodes, plane,
+                       plane * (size_t)(g.nzn - 1), t_mid);
+  }
+  // residual of the node equations for the FP64 solution: |b - A theta| / |b|
+  hipLaunchKernelGGL((th_residual<double, true, R>), dim3(th.nblk), blk, 0, st, g, heat,
+                     (const double*)f1, f0, part);
+  hipLaunchKernelGGL(th_scalars, dim3(1), blk, 0, st, (const double*)part, th.nblk, 0, sc);
+  double hs[kCount];
+  hipError_t e = hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "direct solve");
+  if (resid_out) *resid_out = hs[kBb] > 0.0 ? std::sqrt(hs[kRz] / hs[kBb]) : std::sqrt(hs[kRz]);
+  return SHG_OK;
+}
+
 static int solve_any(Therm& th, const void* heat, void* t_nodes, void* t_mid, double tol,
                      int max_iter, void* ws, int* iters, double* resid, hipStream_t st) {
+  if (th.p.method == SHG_THERMAL_DIRECT) {
+    if (iters) *iters = 0;
+    if (th.dtype == SHG_C64)
+      return solve_direct<float>(th, (const float*)heat, (float*)t_nodes, (float*)t_mid,
+                                 (char*)ws, resid, st);
+    return solve_direct<double>(th, (const double*)heat, (double*)t_nodes, (double*)t_mid,
+                                (char*)ws, resid, st);
+  }
   if (th.dtype == SHG_C64)
     return solve_t<float>(th, (const float*)heat, (float*)t_nodes, (float*)t_mid, tol, max_iter,
                           (char*)ws, iters, resid, st);
@@ -287,6 +494,7 @@ int shg_thermal_destroy(shg_thermal* t) {
   int rc = check_therm(t);
   if (rc) return rc;
   Therm* th = reinterpret_cast<Therm*>(t);
+  free_fdm(th->fdm);
   th->magic = 0;
   delete th;
   return ok();

@@ -122,9 +122,10 @@ __global__ void __launch_bounds__(256) th_init(ThermGeom g, const R* __restrict_
   }
 }
 
-// r = b - A theta, per-block partials of r.z (z = r / diag) and b.b.
-template <typename R>
-__global__ void __launch_bounds__(256) th_residual(ThermGeom g, const R* __restrict__ heat,
+// r = b - A theta, per-block partials of r.z (z = r / diag), or of r.r when
+// RR, and of b.b.
+template <typename R, bool RR = false, typename H = R>
+__global__ void __launch_bounds__(256) th_residual(ThermGeom g, const H* __restrict__ heat,
                                                    const R* __restrict__ theta, R* __restrict__ r,
                                                    double* __restrict__ part) {
   __shared__ double red[4];
@@ -139,7 +140,7 @@ __global__ void __launch_bounds__(256) th_residual(ThermGeom g, const R* __restr
     const double ax = (double)apply_node<R>(g, q, i, [&](size_t j, int) { return theta[j]; });
     const R rr = (R)(b - ax);
     r[i] = rr;
-    rz += (double)rr * (double)rr * g.inv_diag[q.cls];
+    rz += (double)rr * (double)rr * (RR ? 1.0 : g.inv_diag[q.cls]);
     bb += b * b;
   }
   rz = block_sum256(rz, red);
@@ -323,6 +324,80 @@ __global__ void __launch_bounds__(256) th_max_final(const double* __restrict__ p
   for (int k = threadIdx.x; k < nblk; k += 256) m = fmax(m, part[k]);
   m = block_max256(m, red);
   if (threadIdx.x == 0) *out = m;
+}
+
+// ---------------------------------------------------------------- direct solve
+// Fast diagonalisation: the operator divided by the control-volume weights is
+// the Kronecker sum L_x + L_y + L_z of 1-D operators on the free nodes (the
+// oven faces are whole planes), each L_d = W_d^-1 S_d with S_d symmetric
+// tridiagonal.  With W_d^-1/2 S_d W_d^-1/2 = U_d Lambda_d U_d^T:
+//   theta = (Q_z x Q_y x Q_x) [ (P_z x P_y x P_x) f / (lx + ly + lz) ],
+//   P_d = U_d^T W_d^1/2,  Q_d = W_d^-1/2 U_d,  f = b / w = q / k + boundary terms.
+// The mode products are FP64 GEMMs; these kernels gather f, divide by the
+// eigenvalue sums and scatter theta back.
+struct FdmBox {
+  int a[3];                 // first free node per direction
+  int m[3];                 // free nodes per direction
+};
+
+template <typename R>
+__global__ void __launch_bounds__(256) fdm_gather(ThermGeom g, FdmBox bx, const R* __restrict__ heat,
+                                                  double* __restrict__ f) {
+  const size_t n = (size_t)bx.m[0] * bx.m[1] * bx.m[2];
+  for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (size_t)gridDim.x * 256) {
+    const int i = (int)(k % bx.m[0]);
+    const int j = (int)((k / bx.m[0]) % bx.m[1]);
+    const int l = (int)(k / ((size_t)bx.m[0] * bx.m[1]));
+    const int x = bx.a[0] + i, y = bx.a[1] + j, z = bx.a[2] + l;
+    const size_t idx = ((size_t)z * g.ny + y) * g.nx + x;
+    const int cls = node_cls(g, x, y, z);
+    f[k] = (double)heat[idx] * g.inv_k + g.src[cls] / g.w[cls];
+  }
+}
+
+__global__ void __launch_bounds__(256) fdm_divide(FdmBox bx, const double* __restrict__ lx,
+                                                  const double* __restrict__ ly,
+                                                  const double* __restrict__ lz, double* __restrict__ f) {
+  const size_t n = (size_t)bx.m[0] * bx.m[1] * bx.m[2];
+  for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (size_t)gridDim.x * 256) {
+    const int i = (int)(k % bx.m[0]);
+    const int j = (int)((k / bx.m[0]) % bx.m[1]);
+    const int l = (int)(k / ((size_t)bx.m[0] * bx.m[1]));
+    f[k] /= lx[i] + ly[j] + lz[l];
+  }
+}
+
+// theta (0 on oven nodes) in FP64 and in the solver's precision, and
+// T = theta + T_oven.
+template <typename R>
+__global__ void __launch_bounds__(256) fdm_scatter(ThermGeom g, FdmBox bx, const double* __restrict__ u,
+                                                   double t_oven, double* __restrict__ theta64,
+                                                   R* __restrict__ t_out) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < g.n; i += (size_t)gridDim.x * 256) {
+    const NodePos q = node_pos(g, i);
+    double th = 0.0;
+    if (!g.oven[q.cls]) {
+      const size_t k = ((size_t)(q.c[2] - bx.a[2]) * bx.m[1] + (q.c[1] - bx.a[1])) * bx.m[0] +
+                       (q.c[0] - bx.a[0]);
+      th = u[k];
+    }
+    theta64[i] = th;
+    t_out[i] = (R)(th + t_oven);
+  }
+}
+
+// P = U^T W^1/2 and Q = W^-1/2 U (column-major, m x m) from the eigenvectors U
+// (column-major, column j = mode j) and the weights w.
+__global__ void __launch_bounds__(256) fdm_factors(int m, const double* __restrict__ u,
+                                                   const double* __restrict__ w, double* __restrict__ pm,
+                                                   double* __restrict__ qm) {
+  const size_t n = (size_t)m * m;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    const int row = (int)(e % m), col = (int)(e / m);   // element (row, col) at row + col m
+    const double uk = u[e];                              // U(row, col): node row, mode col
+    qm[e] = uk / sqrt(w[row]);                           // Q(row, col)
+    pm[(size_t)row * m + col] = uk * sqrt(w[row]);       // P(col, row) = U(row, col) sqrt(w_row)
+  }
 }
 
 }  // namespace shg

@@ -177,17 +177,22 @@ def test_thermal_params_rejected(lib, bad, needle):
 
 
 def test_thermal_plan_is_host_only_and_sizes_its_workspace(lib):
-    """A thermal plan allocates no device memory, so it is created here; its
-    workspace is seven node vectors plus block partials and scalars."""
-    rc, h, msg = thermal_create(lib)
-    assert rc == binding.SHG_OK, msg
+    """A thermal plan allocates no device memory when it is created, so it is
+    created here; its workspace is seven node vectors plus block partials and
+    scalars, and two FP64 node vectors more for the direct solver."""
     n = 32 * 16 * 9
     vec = (n * 4 + 255) // 256 * 256
-    ws = lib.shg_thermal_workspace_bytes(h)
-    assert 7 * vec < ws < 7 * vec + 64 * 1024
+    vec64 = (n * 8 + 255) // 256 * 256
+    sizes = {}
+    for method in ("cg", "direct"):
+        rc, h, msg = thermal_create(lib, method=method)
+        assert rc == binding.SHG_OK, msg
+        sizes[method] = lib.shg_thermal_workspace_bytes(h)
+        assert lib.shg_thermal_destroy(h) == binding.SHG_OK
+    assert 7 * vec < sizes["cg"] < 7 * vec + 64 * 1024
+    assert sizes["direct"] == sizes["cg"] + 2 * vec64
     rc2, h2, _ = thermal_create(lib, dtype=1)
-    assert lib.shg_thermal_workspace_bytes(h2) > ws
-    assert lib.shg_thermal_destroy(h) == binding.SHG_OK
+    assert lib.shg_thermal_workspace_bytes(h2) > sizes["direct"]
     assert lib.shg_thermal_destroy(h2) == binding.SHG_OK
     # destroyed or foreign handles are refused, not dereferenced as plans
     junk = (ctypes.c_uint64 * 64)()
@@ -195,3 +200,12 @@ def test_thermal_plan_is_host_only_and_sizes_its_workspace(lib):
     it, res = ctypes.c_int32(), ctypes.c_double()
     assert lib.shg_thermal_solve(ctypes.cast(junk, ctypes.c_void_p), None, None, None, 1e-6, 10,
                                  None, ctypes.byref(it), ctypes.byref(res), None) == binding.SHG_ESTATE
+
+
+def test_unknown_thermal_method_rejected(lib):
+    g = dict(nx=32, ny=16, nz=8, lx=1e-3, ly=1e-3, lcr=5e-3)
+    tp = binding.make_thermal_params(g, 5.0, 10.0, 295.0, 330.0, {"y-": "oven"})
+    tp.method = 7
+    h = ctypes.c_void_p()
+    assert lib.shg_thermal_create(ctypes.byref(h), ctypes.byref(tp), 0) == binding.SHG_EINVAL
+    assert "method" in lib.shg_last_error().decode()
