@@ -2,7 +2,7 @@
 the batched sweep (512 instances, sizes 64/128/256 in 1:2:1, nz in [200, 1000]),
 forward + adjoint on the 256 x 256 x 1000 differentiation workload, the heat
 equation for the heat of the 256 x 256 x 1000 march, and the self-consistent
-field <-> temperature loop of the 50 W workload at 256 x 256 x 1000."""
+field <-> temperature loop of the 50 W workload (512 x 512 x 2000)."""
 from __future__ import annotations
 
 import time
@@ -71,44 +71,89 @@ def fwd_adj(device, reps=2):
             "frac_hbm_at_224B": round(wl.cell_steps / sec * 224 / 8e12, 4)}
 
 
-def thermal(device):
-    """Heat equation (open-top oven) for the heat source of the benchmark march:
-    cold start to a relative residual of 1e-6.  Convention: 40 B per node and
-    iteration (direction/stencil pass 16 B, update pass 24 B)."""
+FP64_MFMA_PEAK = 78.6e12
+
+
+def _direct_flops(nx, ny, nzn, faces):
+    """Flops of the six FP64 GEMM mode products of one direct solve."""
+    def free(n, lo, hi):
+        return n - (faces.get(lo) == "oven") - (faces.get(hi) == "oven")
+    m = [free(nx, "x-", "x+"), free(ny, "y-", "y+"), free(nzn, "z-", "z+")]
+    prod = m[0] * m[1] * m[2]
+    return 2 * 2 * sum(md * prod for md in m)
+
+
+def _heat_of_march(wl, device):
     import torch
     import workloads
-    from paper_2410_04994_amd import Plan, Thermal, beams, autotune
-    wl = workloads.c2_plain_c64()
+    from paper_2410_04994_amd import Plan, beams, autotune
     plan = Plan(wl.params(), "c64")
     autotune.tune_single(plan)
-    theta = torch.from_numpy(workloads.phase_noise(wl)).to(device)
+    theta = torch.from_numpy(workloads.phase_noise(wl)).to(device) if wl.phase_noise_std else None
     a = beams.pump_for(wl, theta=theta, dtype=torch.complex64, device=device)
     b = torch.zeros_like(a)
     heat, _ = plan.propagate_heat(a, b)
-    th = Thermal(wl.params(), dtype="c64", **workloads.open_top_oven())
+    return heat
+
+
+def thermal(device, reps=3):
+    """Heat equation (open-top oven) for the heat source of a march.
+      direct  fast diagonalisation: FP64 GEMM mode products on MFMA; roofline
+              against the FP64 MFMA peak (the set-up, once per plan, is timed apart)
+      cg      Jacobi-PCG to a relative residual of 1e-6 from a cold start;
+              convention 40 B per node and iteration"""
+    import torch
+    import workloads
+    from paper_2410_04994_amd import Thermal
+    setup = workloads.open_top_oven()
+    out = {}
+    for wl in (workloads.c2_plain_c64(), workloads.c5_thermal_c64()):
+        heat = _heat_of_march(wl, device)
+        nodes = wl.nx * wl.ny * (wl.nz + 1)
+        th = Thermal(wl.params(), dtype="c64", method="direct", **setup)
+        th.workspace(device)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t, _, _, res = th.solve(heat)
+        torch.cuda.synchronize()
+        first = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            t, _, _, res = th.solve(heat)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        flops = _direct_flops(wl.nx, wl.ny, wl.nz + 1, setup["faces"])
+        out[f"direct_{wl.nx}x{wl.ny}x{wl.nz + 1}"] = {
+            "nodes": nodes, "ms": round(sec * 1e3, 3), "first_solve_ms": round(first * 1e3, 2),
+            "residual": res, "gemm_tflops": round(flops / sec / 1e12, 2),
+            "frac_fp64_mfma": round(flops / sec / FP64_MFMA_PEAK, 4),
+            "t_max_rise_K": round(float(t.max()) - workloads.T_OVEN, 4)}
+        del th, t
+    wl = workloads.c2_plain_c64()
+    heat = _heat_of_march(wl, device)
+    th = Thermal(wl.params(), dtype="c64", method="cg", **setup)
     th.workspace(device)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    t, _, iters, res = th.solve(heat, tol=1e-6, max_iter=40000)
+    _, _, iters, res = th.solve(heat, tol=1e-6, max_iter=40000)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     nodes = wl.nx * wl.ny * (wl.nz + 1)
-    return {"workload": f"heat_equation_{wl.nx}x{wl.ny}x{wl.nz + 1}_open_top_oven",
-            "nodes": nodes, "iterations": iters, "residual": res, "ms": round(sec * 1e3, 2),
-            "node_iterations_per_s": round(nodes * iters / sec, 1),
-            "frac_hbm_at_40B": round(nodes * iters / sec * 40 / 8e12, 4),
-            "t_max_rise_K": round(float(t.max()) - workloads.T_OVEN, 4)}
+    out[f"cg_{wl.nx}x{wl.ny}x{wl.nz + 1}"] = {
+        "iterations": iters, "residual": res, "ms": round(sec * 1e3, 2),
+        "node_iterations_per_s": round(nodes * iters / sec, 1),
+        "frac_hbm_at_40B": round(nodes * iters / sec * 40 / 8e12, 4)}
+    return out
 
 
 def self_consistent_loop(device):
-    """Self-consistent loop of the 50 W temperature-field workload (dk(T), thermal
-    lens) at 256 x 256 x 1000 on the same physical window: until the largest
+    """Self-consistent loop of the 50 W temperature-field workload (512 x 512 x
+    2000, dk(T), thermal lens, open-top oven, direct solver) until the largest
     change of T is below 1 mK."""
     import torch
     import workloads
     from paper_2410_04994_amd import Plan, Thermal, beams, autotune, self_consistent
-    base = workloads.c5_thermal_c64()
-    wl = base.with_(name="c5_thermal_256x256x1000", nx=256, ny=256, nz=1000)
+    wl = workloads.c5_thermal_c64()
     plan = Plan(wl.params(), "c64")
     autotune.tune_single(plan)
     a0 = beams.pump_for(wl, dtype=torch.complex64, device=device)
