@@ -151,6 +151,8 @@ def adjoint(p: dict, a_f0: np.ndarray, a_sh0: np.ndarray, g_f_out: np.ndarray,
     power_weights     : (w_F, w_SH) multiplying the exit powers in L
     Returns g_f, g_sh (gradients at z = 0), g_dk [nz] (per-step mismatch),
     g_temp [nz, ny, nx] when a temperature field is given, and the forward result."""
+    if ssfm.split_order(p) != "NLN":
+        raise NotImplementedError("the oracle adjoint covers the N/2 - L - N/2 split")
     c = ssfm.coefficients(p)
     dz = c.dz
     nz = p["nz"]

@@ -32,11 +32,15 @@ the design notes and pinned by a test in tests/test_oracle_pins.py):
     i.e. a factor exp(-2 i pi qx tan(rho_j) dz) of the propagator.  rho_j comes
     from params "walkoff_f" / "walkoff_sh" (rad, default 0).
 
-Discrete scheme, one z-step s on [z_s, z_s + dz] (Eq. 14, order N/2 - L - N/2):
+Discrete scheme, one z-step s on [z_s, z_s + dz] (Eq. 14, order N/2 - L - N/2,
+the order the paper implements; params "split" = "NLN", the default):
   y <- RK4 over [z_s, z_s + dz/2] of the pointwise nonlinear system
   A_j <- IFFT2( M_j * FFT2(A_j) ),
          M_j = exp[(2 i pi^2 (qx^2 + qy^2)/k_j - alpha_j/2 - 2 i pi qx tan(rho_j)) dz]
   y <- RK4 over [z_s + dz/2, z_s + dz]
+The other Strang order that Sec. 3 calls equivalent (params "split" = "LNL"):
+  A_j <- L(dz/2) A_j;  y <- RK4 over [z_s, z_s + dz];  A_j <- L(dz/2) A_j
+with the same per-step mismatch and temperature sample.
 Grid: x_m = (m - Nx/2) dx, dx = Lx/Nx (periodic window); q = fftfreq(N, dx)
 in cycles per metre, which is the transform pair of Eq. A.2.
 """
@@ -100,6 +104,14 @@ def propagator(p: dict, k: float, alpha: float, dz: float, walkoff: float = 0.0)
     q2 = qy[:, None] ** 2 + qx[None, :] ** 2
     drift = 2j * math.pi * math.tan(walkoff) * qx[None, :]
     return np.exp((2j * math.pi ** 2 * q2 / k - alpha / 2.0 - drift) * dz)
+
+
+def split_order(p: dict) -> str:
+    """"NLN" (N/2 - L - N/2, default) or "LNL" (L/2 - N - L/2)."""
+    order = p.get("split", "NLN")
+    if order not in ("NLN", "LNL"):
+        raise ValueError(f"unknown split order {order!r}")
+    return order
 
 
 def walkoff_angles(p: dict):
@@ -176,8 +188,10 @@ def propagate(p: dict, a_f: np.ndarray, a_sh: np.ndarray, dk_z: Optional[np.ndar
     dz = c.dz
     undepleted = bool(p.get("undepleted", False))
     rho_f, rho_sh = walkoff_angles(p)
-    m_f = propagator(p, c.k_f, p["alpha_f"], dz, rho_f)
-    m_sh = propagator(p, c.k_sh, p["alpha_sh"], dz, rho_sh)
+    lnl = split_order(p) == "LNL"
+    hstep = dz / 2 if lnl else dz
+    m_f = propagator(p, c.k_f, p["alpha_f"], hstep, rho_f)
+    m_sh = propagator(p, c.k_sh, p["alpha_sh"], hstep, rho_sh)
     a = np.array(a_f, dtype=np.complex128)
     b = np.array(a_sh, dtype=np.complex128)
 
@@ -192,10 +206,17 @@ def propagate(p: dict, a_f: np.ndarray, a_sh: np.ndarray, dk_z: Optional[np.ndar
         if return_states:
             states.append((a.copy(), b.copy()))
         dk_s, dT = step_mismatch(p, s, dk_z, temp)
-        a, b = rk4(a, b, phi, dk_s, 0.0, dz / 2, dT, c, undepleted)
-        a = linear_step(a, m_f)
-        b = linear_step(b, m_sh)
-        a, b = rk4(a, b, phi, dk_s, dz / 2, dz / 2, dT, c, undepleted)
+        if lnl:
+            a = linear_step(a, m_f)
+            b = linear_step(b, m_sh)
+            a, b = rk4(a, b, phi, dk_s, 0.0, dz, dT, c, undepleted)
+            a = linear_step(a, m_f)
+            b = linear_step(b, m_sh)
+        else:
+            a, b = rk4(a, b, phi, dk_s, 0.0, dz / 2, dT, c, undepleted)
+            a = linear_step(a, m_f)
+            b = linear_step(b, m_sh)
+            a, b = rk4(a, b, phi, dk_s, dz / 2, dz / 2, dT, c, undepleted)
         phi = phi + dk_s * dz
         if trace:
             tr_f.append(power(a, p["n_f"], c.dx, c.dy))

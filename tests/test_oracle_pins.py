@@ -462,3 +462,55 @@ def test_walkoff_moves_the_centroid_by_tan_rho_z():
     assert abs(cys - cy0) < 1e-12 * p["ly"] and abs(cxf - cx0) < 1e-12 * p["lx"]
     c = ssfm.coefficients(p)
     assert abs(ssfm.power(out["a_sh"], 1.0, c.dx, c.dy) / ssfm.power(a0, 1.0, c.dx, c.dy) - 1) < 1e-12
+
+
+# --------------------------------------------------------------------- split order
+def lnl_case(nz, split, **kw):
+    lcr, xi = 10e-3, 2.0
+    w0 = waist(lcr, xi)
+    p = base_params(n=32, nz=nz, lcr=lcr, width=10 * w0 * math.sqrt(1 + xi * xi), dk0=-120.0,
+                    alpha_f=2.0, alpha_sh=5.0, beta_f=2e-11, beta_sh=2e-11, split=split)
+    p.update(kw)
+    a0 = beams.input_pump(p, 2e3, w0, lcr / 2)
+    return p, a0
+
+
+def test_split_orders_agree_to_second_order():
+    """Sec. 3 calls L/2 - N - L/2 equivalent to the implemented N/2 - L - N/2:
+    both are second-order Strang splittings of the same flow, so on a depleted,
+    lossy march they differ by O(dz^2) (ratio ~4 per halving of dz), and each
+    converges to the same limit."""
+    diffs = []
+    for nz in (50, 100):
+        p, a0 = lnl_case(nz, "NLN")
+        nln = ssfm.propagate(p, a0, np.zeros_like(a0))
+        lnl = ssfm.propagate(dict(p, split="LNL"), a0, np.zeros_like(a0))
+        c = ssfm.coefficients(p)
+        assert nln["p_sh"] > 0.05 * ssfm.power(a0, NF, c.dx, c.dy)
+        diffs.append(rel(lnl["a_sh"], nln["a_sh"]))
+    assert 1e-5 < diffs[1] < 1e-2               # a real O(dz^2) splitting difference
+    assert 3.8 < diffs[0] / diffs[1] < 4.2
+
+
+def test_split_orders_coincide_without_nonlinearity():
+    """With d = 0, no TPA and no temperature, N is the identity and both orders
+    reduce to L^nz exactly."""
+    p, a0 = lnl_case(12, "NLN", d_eff=0.0, beta_f=0.0, beta_sh=0.0)
+    b0 = 0.3 * a0
+    nln = ssfm.propagate(p, a0, b0)
+    lnl = ssfm.propagate(dict(p, split="LNL"), a0, b0)
+    assert rel(lnl["a_f"], nln["a_f"]) < 1e-13 and rel(lnl["a_sh"], nln["a_sh"]) < 1e-13
+
+
+def test_lnl_conserves_energy_without_loss():
+    """Manley-Rowe conservation for the L/2 - N - L/2 order (lossless, no TPA):
+    the drift is RK4 truncation over the full step."""
+    lcr, xi = 10e-3, 1.0
+    w0 = waist(lcr, xi)
+    p = base_params(n=64, nz=400, lcr=lcr, width=12 * w0 * math.sqrt(2), split="LNL")
+    a0 = beams.input_pump(p, 3e3, w0, lcr / 2)
+    out = ssfm.propagate(p, a0, np.zeros_like(a0), trace=True)
+    c = ssfm.coefficients(p)
+    p0 = ssfm.power(a0, NF, c.dx, c.dy)
+    assert out["trace_sh"][-1] / p0 > 0.3
+    assert np.max(np.abs((out["trace_f"] + out["trace_sh"]) / p0 - 1)) < 1e-9

@@ -63,6 +63,7 @@ class Workload:
     t_ref: float = 0.0
     walkoff_f: float = 0.0         # spatial walk-off angle of the fundamental [rad]
     walkoff_sh: float = 0.0        # spatial walk-off angle of the SH [rad]
+    split: str = "NLN"             # Strang order: "NLN" (the paper's) or "LNL"
     undepleted: bool = False
     phase_noise_std: float = 0.0   # std of the i.i.d. input phase mask [rad]
     seed: int = 0
@@ -74,7 +75,7 @@ class Workload:
         """Plain parameter dict understood by both the oracle and the binding."""
         keys = ("nx", "ny", "nz", "lx", "ly", "lcr", "lambda_f", "n_f", "n_sh", "d_eff",
                 "alpha_f", "alpha_sh", "beta_f", "beta_sh", "dk0", "ddk_dT", "dn_dT",
-                "t_ref", "walkoff_f", "walkoff_sh", "undepleted")
+                "t_ref", "walkoff_f", "walkoff_sh", "split", "undepleted")
         return {k: getattr(self, k) for k in keys}
 
     @property
