@@ -64,8 +64,15 @@ enum {
 /* flags */
 enum {
   SHG_UNDEPLETED = 1u << 0, /* undepleted pump: dA_F/dz has no nonlinear part */
-  SHG_NO_GRAPH = 1u << 1    /* launch passes one by one instead of replaying a
+  SHG_NO_GRAPH = 1u << 1,   /* launch passes one by one instead of replaying a
                                cached HIP graph of the whole march              */
+  SHG_SPLIT_LNL = 1u << 2   /* the other Strang order of Sec. 3, L/2 - N - L/2:
+                               one RK4 over dz per step (stages at 0, dz/2, dz)
+                               between two half-step propagators; interior
+                               half-steps merge into one column pass.  Not with
+                               shg_propagate_adjoint or shg_propagate_heat
+                               (SHG_EUNSUPPORTED); all plans of a batch share
+                               the order                                        */
 };
 
 typedef struct {

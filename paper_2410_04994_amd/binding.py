@@ -18,6 +18,7 @@ SHG_C64, SHG_C128 = 0, 1
 SHG_OK, SHG_EINVAL, SHG_EUNSUPPORTED, SHG_ENOMEM, SHG_EDEVICE, SHG_ESTATE = range(6)
 SHG_UNDEPLETED = 1 << 0
 SHG_NO_GRAPH = 1 << 1
+SHG_SPLIT_LNL = 1 << 2
 ERROR_NAMES = {0: "SHG_OK", 1: "SHG_EINVAL", 2: "SHG_EUNSUPPORTED", 3: "SHG_ENOMEM",
                4: "SHG_EDEVICE", 5: "SHG_ESTATE"}
 
@@ -146,6 +147,11 @@ def make_params(params: dict, flags: int = 0, checkpoint_every: int = 0) -> ShgP
     f = flags
     if params.get("undepleted"):
         f |= SHG_UNDEPLETED
+    split = params.get("split", "NLN")
+    if split not in ("NLN", "LNL"):
+        raise ValueError(f"unknown split order {split!r}")
+    if split == "LNL":
+        f |= SHG_SPLIT_LNL
     p.flags = f
     p.checkpoint_every = int(checkpoint_every)
     return p

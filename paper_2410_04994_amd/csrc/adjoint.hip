@@ -324,6 +324,8 @@ int propagate_adjoint(Plan& pl, const void* a_f_in, const void* a_sh_in, const d
   if (!g_f_in || !g_sh_in) return fail(SHG_EINVAL, "g_f_in and g_sh_in must be non-NULL");
   if (!ws) return fail(SHG_EINVAL, "workspace must be non-NULL (shg_workspace_bytes(plan, 1))");
   if (g_t && !temp) return fail(SHG_EINVAL, "g_t_moments requires a temperature field");
+  if (pl.p.flags & SHG_SPLIT_LNL)
+    return fail(SHG_EUNSUPPORTED, "the adjoint covers the N/2 - L - N/2 split");
   int rc = sticky_device_error();
   if (rc) return rc;
   if (pl.dtype == SHG_C64)

@@ -60,14 +60,14 @@ bool brow_try(int e, int wg, const BatchInst<R>* d, int count, int s, int blocks
 }
 
 template <typename R, int N, int E, int TC>
-bool bcol_try(int e, int tc, const BatchInst<R>* d, int count, int blocks, hipStream_t st) {
+bool bcol_try(int e, int tc, const BatchInst<R>* d, int count, int s, int blocks, hipStream_t st) {
   if constexpr (bcol_valid<R, N, E, TC>()) {
     if (e != E || tc != TC) return false;
     hipLaunchKernelGGL((col_pass_batch<R, N, N / E, TC>), dim3(blocks, count),
-                       dim3((N / E) * TC), 0, st, d);
+                       dim3((N / E) * TC), 0, st, d, s);
     return true;
   } else {
-    (void)e; (void)tc; (void)d; (void)count; (void)blocks; (void)st;
+    (void)e; (void)tc; (void)d; (void)count; (void)s; (void)blocks; (void)st;
     return false;
   }
 }
@@ -99,15 +99,15 @@ bool brow_n(int e, int wg, const BatchInst<R>* d, int c, int s, int b, hipStream
 }
 
 template <typename R, int N>
-bool bcol_n(int e, int tc, const BatchInst<R>* d, int c, int b, hipStream_t st) {
-  return bcol_try<R, N, 4, 1>(e, tc, d, c, b, st) || bcol_try<R, N, 4, 2>(e, tc, d, c, b, st) ||
-         bcol_try<R, N, 4, 4>(e, tc, d, c, b, st) || bcol_try<R, N, 4, 8>(e, tc, d, c, b, st) ||
-         bcol_try<R, N, 4, 16>(e, tc, d, c, b, st) || bcol_try<R, N, 8, 1>(e, tc, d, c, b, st) ||
-         bcol_try<R, N, 8, 2>(e, tc, d, c, b, st) || bcol_try<R, N, 8, 4>(e, tc, d, c, b, st) ||
-         bcol_try<R, N, 8, 8>(e, tc, d, c, b, st) || bcol_try<R, N, 8, 16>(e, tc, d, c, b, st) ||
-         bcol_try<R, N, 16, 1>(e, tc, d, c, b, st) || bcol_try<R, N, 16, 2>(e, tc, d, c, b, st) ||
-         bcol_try<R, N, 16, 4>(e, tc, d, c, b, st) || bcol_try<R, N, 16, 8>(e, tc, d, c, b, st) ||
-         bcol_try<R, N, 16, 16>(e, tc, d, c, b, st);
+bool bcol_n(int e, int tc, const BatchInst<R>* d, int c, int s, int b, hipStream_t st) {
+  return bcol_try<R, N, 4, 1>(e, tc, d, c, s, b, st) || bcol_try<R, N, 4, 2>(e, tc, d, c, s, b, st) ||
+         bcol_try<R, N, 4, 4>(e, tc, d, c, s, b, st) || bcol_try<R, N, 4, 8>(e, tc, d, c, s, b, st) ||
+         bcol_try<R, N, 4, 16>(e, tc, d, c, s, b, st) || bcol_try<R, N, 8, 1>(e, tc, d, c, s, b, st) ||
+         bcol_try<R, N, 8, 2>(e, tc, d, c, s, b, st) || bcol_try<R, N, 8, 4>(e, tc, d, c, s, b, st) ||
+         bcol_try<R, N, 8, 8>(e, tc, d, c, s, b, st) || bcol_try<R, N, 8, 16>(e, tc, d, c, s, b, st) ||
+         bcol_try<R, N, 16, 1>(e, tc, d, c, s, b, st) || bcol_try<R, N, 16, 2>(e, tc, d, c, s, b, st) ||
+         bcol_try<R, N, 16, 4>(e, tc, d, c, s, b, st) || bcol_try<R, N, 16, 8>(e, tc, d, c, s, b, st) ||
+         bcol_try<R, N, 16, 16>(e, tc, d, c, s, b, st);
 }
 
 template <typename R>
@@ -124,14 +124,14 @@ bool brow(int n, int e, int wg, const BatchInst<R>* d, int c, int s, int b, hipS
 }
 
 template <typename R>
-bool bcol(int n, int e, int tc, const BatchInst<R>* d, int c, int b, hipStream_t st) {
+bool bcol(int n, int e, int tc, const BatchInst<R>* d, int c, int s, int b, hipStream_t st) {
   switch (n) {
-    case 16: return bcol_n<R, 16>(e, tc, d, c, b, st);
-    case 32: return bcol_n<R, 32>(e, tc, d, c, b, st);
-    case 64: return bcol_n<R, 64>(e, tc, d, c, b, st);
-    case 128: return bcol_n<R, 128>(e, tc, d, c, b, st);
-    case 256: return bcol_n<R, 256>(e, tc, d, c, b, st);
-    case 512: return bcol_n<R, 512>(e, tc, d, c, b, st);
+    case 16: return bcol_n<R, 16>(e, tc, d, c, s, b, st);
+    case 32: return bcol_n<R, 32>(e, tc, d, c, s, b, st);
+    case 64: return bcol_n<R, 64>(e, tc, d, c, s, b, st);
+    case 128: return bcol_n<R, 128>(e, tc, d, c, s, b, st);
+    case 256: return bcol_n<R, 256>(e, tc, d, c, s, b, st);
+    case 512: return bcol_n<R, 512>(e, tc, d, c, s, b, st);
     default: return false;
   }
 }
@@ -148,6 +148,7 @@ struct Group {
 };
 
 struct BatchPlanInfo {
+  bool lnl = false;                          // every plan uses the L/2 - N - L/2 order
   std::vector<Group> groups;
   std::vector<std::vector<int>> branches;   // group indices per stream
   std::vector<int> order;     // descriptor slot -> caller index
@@ -174,6 +175,7 @@ static int build_info(int n, shg_plan* const* plans, BatchPlanInfo& bi) {
         .push_back(i);
   }
   const Plan& p0 = *reinterpret_cast<const Plan*>(plans[0]);
+  bi.lnl = (p0.p.flags & SHG_SPLIT_LNL) != 0;
   const size_t csize = 2 * (size_t)p0.real_bytes;
   const size_t inst_bytes = p0.dtype == SHG_C64 ? sizeof(BatchInst<float>) : sizeof(BatchInst<double>);
   bi.groups.clear();
@@ -238,6 +240,8 @@ static int validate_batch(int n, shg_plan* const* plans, void* const* a_f, void*
     const Plan& pl = *reinterpret_cast<const Plan*>(plans[i]);
     const Plan& p0 = *reinterpret_cast<const Plan*>(plans[0]);
     if (pl.dtype != p0.dtype) return fail(SHG_EINVAL, "plans[%d] dtype differs from plans[0]", i);
+    if ((pl.p.flags & SHG_SPLIT_LNL) != (p0.p.flags & SHG_SPLIT_LNL))
+      return fail(SHG_EINVAL, "plans[%d] uses another split order than plans[0]", i);
   }
   return SHG_OK;
 }
@@ -278,6 +282,11 @@ static int enqueue_batch(int n, shg_plan* const* plans, void* const* a_f, void* 
       c.nx = pl.p.nx;
       c.tiles = pl.p.nx / pl.b_col_tc;
       c.conj_prop = 0;
+      I.lnl = (pl.p.flags & SHG_SPLIT_LNL) ? 1 : 0;
+      for (int w = 0; w < 2; ++w) {
+        I.mxh[w] = pl.mxh[w];
+        I.myh[w] = pl.myh[w];
+      }
       I.dk_z = dk_z ? dk_z[i] : nullptr;
       I.dk0 = pl.p.dk0;
       I.dz = pl.dz;
@@ -308,6 +317,17 @@ static int enqueue_batch(int n, shg_plan* const* plans, void* const* a_f, void* 
     hipStream_t bs = fork ? side->side[b] : st;
     int max_nz = 0;
     for (int gi : bi.branches[b]) max_nz = std::max(max_nz, bi.groups[gi].nzs[0]);
+    if (bi.lnl) {
+      // L/2 - N - L/2: opening FFT_x and half-step column pass of every instance
+      for (int gi : bi.branches[b]) {
+        const Group& g = bi.groups[gi];
+        const int cnt = (int)g.nzs.size();
+        if (!brow<R>(g.nx, g.re, g.rw, dev + g.offset, cnt, -1, g.ny / g.rows, bs))
+          return fail(SHG_EUNSUPPORTED, "batched row schedule not built");
+        if (!bcol<R>(g.ny, g.ce, g.ct, dev + g.offset, cnt, -1, 2 * (g.nx / g.ct), bs))
+          return fail(SHG_EUNSUPPORTED, "batched column schedule not built");
+      }
+    }
     for (int s = 0; s <= max_nz; ++s) {
       for (int gi : bi.branches[b]) {
         const Group& g = bi.groups[gi];
@@ -325,7 +345,7 @@ static int enqueue_batch(int n, shg_plan* const* plans, void* const* a_f, void* 
         const int cnt = (int)(std::lower_bound(g.nzs.begin(), g.nzs.end(), s, std::greater<int>()) -
                               g.nzs.begin());
         if (cnt == 0) continue;
-        if (!bcol<R>(g.ny, g.ce, g.ct, dev + g.offset, cnt, 2 * (g.nx / g.ct), bs))
+        if (!bcol<R>(g.ny, g.ce, g.ct, dev + g.offset, cnt, s, 2 * (g.nx / g.ct), bs))
           return fail(SHG_EUNSUPPORTED, "batched column schedule not built");
       }
     }

@@ -41,13 +41,16 @@ struct HalfStep {
   cx<R> cf[3], cs[3];
 };
 
-// e = exp(-i phi): cf = i kappa_F e, cs = i kappa_SH conj(e)
+// e = exp(-i phi): cf = i kappa_F e, cs = i kappa_SH conj(e).  The stage
+// points are e[0], e[stride], e[2 stride] of the step's 5-point table: stride 1
+// for a half-step, 2 for a full step (L/2 - N - L/2 order).
 template <typename R>
-__device__ __forceinline__ HalfStep<R> half_step_coefs(const cx<R>* __restrict__ e, R kf, R ks) {
+__device__ __forceinline__ HalfStep<R> half_step_coefs(const cx<R>* __restrict__ e, R kf, R ks,
+                                                       int stride = 1) {
   HalfStep<R> h;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const cx<R> ek = e[k];
+    const cx<R> ek = e[k * stride];
     h.cf[k] = {-kf * ek.im, kf * ek.re};
     h.cs[k] = {ks * ek.im, ks * ek.re};
   }
@@ -85,11 +88,12 @@ struct HalfStepT {
 __device__ __forceinline__ void sincos_r(float x, float* s, float* c) { sincosf(x, s, c); }
 __device__ __forceinline__ void sincos_r(double x, double* s, double* c) { sincos(x, s, c); }
 
-// Stage coefficients at tau0, tau0 + dz/4, tau0 + dz/2 for one cell.
+// Stage coefficients at tau0, tau0 + qdz, tau0 + 2 qdz for one cell (qdz =
+// dz/4 and stride 1 for a half-step; dz/2 and stride 2 for a full step).
 template <typename R>
 __device__ __forceinline__ HalfStepT<R> thermal_coefs(const cx<R>* __restrict__ e, R kf, R ks,
                                                       R ddk, R psi, R dT, R tau0, R qdz,
-                                                      R lens_f, R lens_sh) {
+                                                      R lens_f, R lens_sh, int stride = 1) {
   HalfStepT<R> h;
   R sn, c;
   sincos_r(ddk * (psi + dT * tau0), &sn, &c);
@@ -98,7 +102,7 @@ __device__ __forceinline__ HalfStepT<R> thermal_coefs(const cx<R>* __restrict__ 
   const cx<R> step = {c, -sn};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const cx<R> ek = e[k] * rho;
+    const cx<R> ek = e[k * stride] * rho;
     h.cf[k] = {-kf * ek.im, kf * ek.re};
     h.cs[k] = {ks * ek.im, ks * ek.re};
     rho = rho * step;
@@ -151,6 +155,7 @@ struct RowArgs {
   int s_first;            // step whose first half-step runs here, or -1
   int inv_in;             // apply IFFT_x after loading
   int fwd_out;            // apply FFT_x before storing
+  int full;               // s_first runs a whole step over dz (L/2 - N - L/2 order)
   R kf, ks;               // kappa_F, kappa_SH
   R tf, ts;               // beta~_F / 2, beta~_SH / 2
   R h;                    // dz / 2
@@ -257,13 +262,16 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
       if (p.heat) p.heat[idx] = heat_density(va[m], vb[m], p);
       if (p.s_first >= 0) {
         const R dT = p.temp[(size_t)p.s_first * n2 + idx] - p.t_ref;
+        const int st = p.full ? 2 : 1;
         const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, p.ddk, psi, dT,
-                                             (R)0, qdz, p.lens_f, p.lens_sh);
-        rk4_cell_t(va[m], vb[m], c, p.tf, p.ts, p.h, und);
+                                             (R)0, qdz * st, p.lens_f, p.lens_sh, st);
+        rk4_cell_t(va[m], vb[m], c, p.tf, p.ts, p.h * st, und);
+        if (p.full) psi += dT * p.dz;
       }
       // psi now holds Psi at the start of the newest step touched (s_first, or
-      // s_second + 1 after a last pass), so a march [s0, s1) leaves Psi_{s1}
-      if (p.s_second >= 0) p.psi[idx] = psi;
+      // s_second + 1 after a last pass, or s_first + 1 after a full step), so a
+      // march [s0, s1) leaves Psi_{s1}
+      if (p.s_second >= 0 || (p.full && p.s_first >= 0)) p.psi[idx] = psi;
     }
   } else {
     if (p.s_second >= 0) {
@@ -276,9 +284,10 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
       for (int m = 0; m < E; ++m) p.heat[row + t + G * m] = heat_density(va[m], vb[m], p);
     }
     if (p.s_first >= 0) {
-      const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks);
+      const int st = p.full ? 2 : 1;
+      const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, st);
 #pragma unroll
-      for (int m = 0; m < E; ++m) rk4_cell(va[m], vb[m], c, p.tf, p.ts, p.h, und);
+      for (int m = 0; m < E; ++m) rk4_cell(va[m], vb[m], c, p.tf, p.ts, p.h * st, und);
     }
   }
   if (p.fwd_out) {
@@ -399,11 +408,13 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
     if (p.heat) p.heat[idx] = heat_density(a, b, p);
     if (p.s_first >= 0) {
       const R dT = p.temp[(size_t)p.s_first * n2 + idx] - p.t_ref;
+      const int st = p.full ? 2 : 1;
       const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, p.ddk, psi, dT,
-                                           (R)0, qdz, p.lens_f, p.lens_sh);
-      rk4_cell_t(a, b, c, p.tf, p.ts, p.h, und);
+                                           (R)0, qdz * st, p.lens_f, p.lens_sh, st);
+      rk4_cell_t(a, b, c, p.tf, p.ts, p.h * st, und);
+      if (p.full) psi += dT * p.dz;
     }
-    if (p.s_second >= 0) p.psi[idx] = psi;
+    if (p.s_second >= 0 || (p.full && p.s_first >= 0)) p.psi[idx] = psi;
   } else {
     if (p.s_second >= 0) {
       const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);
@@ -411,8 +422,9 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
     }
     if (p.heat) p.heat[idx] = heat_density(a, b, p);
     if (p.s_first >= 0) {
-      const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks);
-      rk4_cell(a, b, c, p.tf, p.ts, p.h, und);
+      const int st = p.full ? 2 : 1;
+      const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, st);
+      rk4_cell(a, b, c, p.tf, p.ts, p.h * st, und);
     }
   }
   if (p.fwd_out) {
@@ -593,22 +605,42 @@ struct BatchInst {
   double* powers;         // [2] or null
   int nz;
   int row_blocks;
+  int lnl;                // L/2 - N - L/2 order
+  const double* mxh[2];   // half-step propagator factors (lnl)
+  const double* myh[2];
 };
 
-// Row pass at boundary s (0 <= s <= nz): second half-step of s-1 when s >= 1,
-// first half-step of s when s < nz; the last boundary leaves real space and
-// writes the power partials.
+// Roles of the row pass at boundary s of one instance.
+//   N/2 - L - N/2 (0 <= s <= nz): second half-step of s-1 when s >= 1, first
+//     half-step of s when s < nz; the last boundary leaves real space and
+//     writes the power partials.
+//   L/2 - N - L/2: s = -1 is the opening FFT_x; 0 <= s < nz runs the whole
+//     step s between IFFT_x and FFT_x; s = nz is the closing IFFT_x.
+template <typename R>
+__device__ __forceinline__ void batch_row_roles(const BatchInst<R>& I, int s, RowArgs<R>& p) {
+  const int nz = I.nz;
+  if (I.lnl) {
+    p.full = 1;
+    p.s_second = -1;
+    p.s_first = (s >= 0 && s < nz) ? s : -1;
+    p.inv_in = s >= 0 ? 1 : 0;
+    p.fwd_out = s < nz ? 1 : 0;
+  } else {
+    p.full = 0;
+    p.s_second = s >= 1 ? s - 1 : -1;
+    p.s_first = s < nz ? s : -1;
+    p.inv_in = s >= 1 ? 1 : 0;
+    p.fwd_out = s < nz ? 1 : 0;
+  }
+  p.partials = (s == nz && I.powers) ? I.partials : nullptr;
+}
+
 template <typename R, int N, int G, int ROWS>
 __global__ void __launch_bounds__(G * ROWS) row_pass_batch(const BatchInst<R>* __restrict__ inst,
                                                            int s) {
   const BatchInst<R>& I = inst[blockIdx.y];
   RowArgs<R> p = I.row;
-  const int nz = I.nz;
-  p.s_second = s >= 1 ? s - 1 : -1;
-  p.s_first = s < nz ? s : -1;
-  p.inv_in = s >= 1 ? 1 : 0;
-  p.fwd_out = s < nz ? 1 : 0;
-  p.partials = (s == nz && I.powers) ? I.partials : nullptr;
+  batch_row_roles(I, s, p);
   row_body<R, N, G, ROWS>(p, blockIdx.x);
 }
 
@@ -617,18 +649,27 @@ __global__ void __launch_bounds__(WideShape<N>::threads) row_pass_batch_wide(
     const BatchInst<R>* __restrict__ inst, int s) {
   const BatchInst<R>& I = inst[blockIdx.y];
   RowArgs<R> p = I.row;
-  const int nz = I.nz;
-  p.s_second = s >= 1 ? s - 1 : -1;
-  p.s_first = s < nz ? s : -1;
-  p.inv_in = s >= 1 ? 1 : 0;
-  p.fwd_out = s < nz ? 1 : 0;
-  p.partials = (s == nz && I.powers) ? I.partials : nullptr;
+  batch_row_roles(I, s, p);
   row_wide_body<R, N, false>(p, blockIdx.x);
 }
 
+// Column pass after row boundary s: the full-step propagator, or in the
+// L/2 - N - L/2 order the half-step one for the opening (s = -1) and the
+// instance's last step (s = nz - 1).
 template <typename R, int N, int G, int TC>
-__global__ void __launch_bounds__(G * TC) col_pass_batch(const BatchInst<R>* __restrict__ inst) {
-  col_body<R, N, G, TC>(inst[blockIdx.y].col);
+__global__ void __launch_bounds__(G * TC) col_pass_batch(const BatchInst<R>* __restrict__ inst,
+                                                         int s) {
+  const BatchInst<R>& I = inst[blockIdx.y];
+  if (I.lnl && (s < 0 || s == I.nz - 1)) {
+    ColArgs<R> c = I.col;
+    for (int w = 0; w < 2; ++w) {
+      c.mx[w] = I.mxh[w];
+      c.my[w] = I.myh[w];
+    }
+    col_body<R, N, G, TC>(c);
+  } else {
+    col_body<R, N, G, TC>(I.col);
+  }
 }
 
 template <typename R>

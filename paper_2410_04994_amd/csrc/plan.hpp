@@ -45,6 +45,8 @@ struct Plan {
   void* tw_y = nullptr;          // W_ny^k
   double* mx[2] = {nullptr, nullptr};
   double* my[2] = {nullptr, nullptr};
+  double* mxh[2] = {nullptr, nullptr};   // half-step factors (L/2 - N - L/2 order)
+  double* myh[2] = {nullptr, nullptr};
   // schedule
   int row_e = 0, row_wg = 0, row_rows = 1;
   int adj_e = 0, adj_wg = 0;     // adjoint row pass

@@ -361,7 +361,7 @@ int validate_params(const shg_params* p) {
   if (p->checkpoint_every < 0) return fail(SHG_EINVAL, "checkpoint_every must be >= 0");
   if (!(std::fabs(p->walkoff_f) < M_PI / 2) || !(std::fabs(p->walkoff_sh) < M_PI / 2))
     return fail(SHG_EINVAL, "walk-off angles must be finite with |rho| < pi/2");
-  if (p->flags & ~(uint32_t)(SHG_UNDEPLETED | SHG_NO_GRAPH))
+  if (p->flags & ~(uint32_t)(SHG_UNDEPLETED | SHG_NO_GRAPH | SHG_SPLIT_LNL))
     return fail(SHG_EINVAL, "unknown flag bits 0x%x", p->flags);
   return SHG_OK;
 }
@@ -428,6 +428,13 @@ int build_plan(Plan& pl) {
     auto my = prop_factor(p.ny, pl.dy, pl.dz, ks[w], std::exp(-al[w] * pl.dz / 2.0) * norm);
     if ((rc = upload((void**)&pl.mx[w], mx.data(), mx.size() * sizeof(double)))) return rc;
     if ((rc = upload((void**)&pl.my[w], my.data(), my.size() * sizeof(double)))) return rc;
+    if (p.flags & SHG_SPLIT_LNL) {
+      const double hz = pl.dz / 2.0;
+      auto mxh = prop_factor(p.nx, pl.dx, hz, ks[w], 1.0, std::tan(rho[w]));
+      auto myh = prop_factor(p.ny, pl.dy, hz, ks[w], std::exp(-al[w] * hz / 2.0) * norm);
+      if ((rc = upload((void**)&pl.mxh[w], mxh.data(), mxh.size() * sizeof(double)))) return rc;
+      if ((rc = upload((void**)&pl.myh[w], myh.data(), myh.size() * sizeof(double)))) return rc;
+    }
   }
   default_schedule(pl);
   if (pl.row_e == 0 || pl.col_e == 0)
@@ -448,12 +455,14 @@ void free_plan_tables(Plan& pl) {
   pl.gexec = nullptr;
   if (pl.cap_stream) (void)hipStreamDestroy(pl.cap_stream);
   pl.cap_stream = nullptr;
-  void* ptrs[] = {pl.tw_x, pl.tw_y, pl.mx[0], pl.mx[1], pl.my[0], pl.my[1], pl.own_ws,
+  void* ptrs[] = {pl.tw_x, pl.tw_y, pl.mx[0], pl.mx[1], pl.my[0], pl.my[1], pl.mxh[0], pl.mxh[1],
+                  pl.myh[0], pl.myh[1], pl.own_ws,
                   pl.batch_ws};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   pl.tw_x = pl.tw_y = nullptr;
   pl.mx[0] = pl.mx[1] = pl.my[0] = pl.my[1] = nullptr;
+  pl.mxh[0] = pl.mxh[1] = pl.myh[0] = pl.myh[1] = nullptr;
   pl.own_ws = nullptr;
   pl.batch_ws = nullptr;
   free_adjoint(pl);
@@ -530,6 +539,52 @@ static int enqueue_forward_t(Plan& pl, const FwdIO& io, const double* dk_z, int 
   ca.conj_prop = 0;
   int rows = 1;
   LaunchTimer tm{&pl};
+  if (p.flags & SHG_SPLIT_LNL) {
+    // L/2 - N - L/2: FFT_x, half-step column pass, then per step the whole
+    // nonlinear step between IFFT_x and FFT_x and a column pass (half-step for
+    // the last), and a closing IFFT_x
+    ColArgs<R> ch = ca;
+    for (int w = 0; w < 2; ++w) {
+      ch.mx[w] = pl.mxh[w];
+      ch.my[w] = pl.myh[w];
+    }
+    ra.ain = (const cx<R>*)io.a_in;
+    ra.bin = (const cx<R>*)io.b_in;
+    ra.aout = wa;
+    ra.bout = wb;
+    ra.tap_a = ra.tap_b = nullptr;
+    ra.s_second = ra.s_first = -1;
+    ra.full = 1;
+    ra.inv_in = 0;
+    ra.fwd_out = 1;
+    ra.partials = nullptr;
+    ra.heat = nullptr;
+    if (!row_dispatch<R>(p.nx, pl.row_e, pl.row_wg, &ra, st, &rows, &tm))
+      return fail(SHG_EUNSUPPORTED, "row schedule e=%d wg=%d not built", pl.row_e, pl.row_wg);
+    if (!col_dispatch<R>(p.ny, pl.col_e, pl.col_tc, &ch, st, &tm))
+      return fail(SHG_EUNSUPPORTED, "column schedule e=%d tc=%d not built", pl.col_e, pl.col_tc);
+    ra.ain = wa;
+    ra.bin = wb;
+    ra.inv_in = 1;
+    for (int s = s0; s < s1; ++s) {
+      ra.s_first = s;
+      row_dispatch<R>(p.nx, pl.row_e, pl.row_wg, &ra, st, &rows, &tm);
+      col_dispatch<R>(p.ny, pl.col_e, pl.col_tc, s == s1 - 1 ? &ch : &ca, st, &tm);
+    }
+    ra.s_first = -1;
+    ra.fwd_out = 0;
+    ra.aout = (cx<R>*)io.a_out;
+    ra.bout = (cx<R>*)io.b_out;
+    ra.partials = powers ? partials : nullptr;
+    row_dispatch<R>(p.nx, pl.row_e, pl.row_wg, &ra, st, &rows, &tm);
+    if (powers) {
+      hipLaunchKernelGGL(power_finalize, dim3(1), dim3(256), 0, st, (const double*)partials,
+                         p.ny / rows, pl.pscale_f, pl.pscale_sh, powers);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return SHG_OK;
+  }
   // first row pass: N(dz/2) of step s0, then FFT_x
   ra.ain = (const cx<R>*)io.a_in;
   ra.bin = (const cx<R>*)io.b_in;
@@ -779,6 +834,8 @@ int shg_propagate_heat(shg_plan* plan, void* a_f, void* a_sh, const double* dk_z
   if (rc) return rc;
   if (!heat) return fail(SHG_EINVAL, "heat must be a non-NULL device pointer");
   Plan* pl = reinterpret_cast<Plan*>(plan);
+  if (pl->p.flags & SHG_SPLIT_LNL)
+    return fail(SHG_EUNSUPPORTED, "the heat source output needs the N/2 - L - N/2 split");
   rc = propagate(*pl, a_f, a_sh, dk_z, temp, 0, pl->p.nz, workspace, powers,
                  (hipStream_t)stream, heat);
   return rc ? rc : ok();

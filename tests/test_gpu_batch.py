@@ -152,3 +152,31 @@ def test_batch_argument_errors():
         propagate_batch([p64, p128], [a, b], [a, b])
     with pytest.raises(ShgError, match="SHG_EINVAL"):
         propagate_batch([], [], [])
+
+
+def test_lnl_batch_matches_single_marches_and_oracle():
+    """A mixed-size batch in the L/2 - N - L/2 order: every instance equals its
+    single-instance march (same schedule) bit for bit, and matches the oracle."""
+    from paper_2410_04994_amd import Plan
+    wls = [w.with_(split="LNL") for w in small_batch(n=9, seed=13, max_nz=20)]
+    plans, ins, a_out, b_out, pw = run_batch(wls)
+    for i, w in enumerate(wls):
+        single = Plan(w.params(), "c64")
+        single.set_schedule(*batch_schedule(plans[i]))
+        a = torch.from_numpy(ins[i][0]).cuda()
+        b = torch.from_numpy(ins[i][1]).cuda()
+        single.propagate(a, b)
+        assert np.array_equal(a.cpu().numpy(), a_out[i]) and np.array_equal(b.cpu().numpy(), b_out[i])
+    for i in (0, 4, 8):
+        ref = run_oracle(wls[i], ins[i][0], ins[i][1])
+        compare(wls[i], (a_out[i], b_out[i], pw[i]), ref, "c64", f"lnl batch {i}")
+
+
+def test_batch_rejects_mixed_split_orders():
+    from paper_2410_04994_amd import Plan, ShgError, propagate_batch
+    wls = small_batch(n=2, seed=3, max_nz=5)
+    plans = [Plan(wls[0].params(), "c64"), Plan(wls[1].with_(split="LNL").params(), "c64")]
+    a = [torch.ones((w.ny, w.nx), dtype=torch.complex64, device="cuda") for w in wls]
+    b = [torch.zeros_like(x) for x in a]
+    with pytest.raises(ShgError, match="split"):
+        propagate_batch(plans, a, b)

@@ -245,3 +245,46 @@ def test_spatial_walkoff(dtype):
     plain = run_oracle(wl.with_(walkoff_sh=0.0, walkoff_f=0.0), a0, b0)
     walk = run_oracle(wl, a0, b0)
     assert rel(walk["a_sh"], plain["a_sh"]) > 1e-2
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_lnl_split_order(dtype):
+    """The L/2 - N - L/2 order (SHG_SPLIT_LNL): one RK4 over dz per step between
+    half-step propagators, with a per-step mismatch profile and walk-off."""
+    base = workloads.c2_plain_c64()
+    wl = base.with_(nx=64, ny=64, nz=50, split="LNL", walkoff_sh=0.05 * base.lx / base.lcr)
+    rng = np.random.Generator(np.random.PCG64(5))
+    dk = wl.dk0 + 200.0 * rng.normal(size=wl.nz)
+    parity(wl, dtype, dk_z=dk)
+    # it is a different discrete scheme: the N/2 - L - N/2 result differs
+    a0, b0 = inputs(wl, dtype)
+    lnl = run_oracle(wl, a0, b0, dk_z=dk)
+    nln = run_oracle(wl.with_(split="NLN"), a0, b0, dk_z=dk)
+    assert rel(lnl["a_sh"], nln["a_sh"]) > 1e-6
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_lnl_with_temperature_field_and_resume(dtype):
+    wl, temp = thermal_case(n=32, nz=24)
+    wl = wl.with_(split="LNL")
+    plan = make_plan(wl, dtype)
+    a0, b0 = inputs(wl, dtype)
+    full = run_gpu(plan, a0, b0, temp=temp)
+    ref = run_oracle(wl, a0, b0, temp=temp.astype(np.float64))
+    compare(wl, full, ref, dtype, "lnl thermal")
+    part = run_gpu(plan, a0, b0, temp=temp, s_end=10)
+    rest = run_gpu(plan, part[0], part[1], temp=temp, s_begin=10)
+    # L/2 L/2 across the split point equals one L up to rounding
+    assert rel(rest[1], full[1]) < (1e-5 if dtype == "c64" else 1e-12)
+
+
+def test_lnl_refuses_adjoint_and_heat_output():
+    from paper_2410_04994_amd import ShgError
+    wl = workloads.c2_plain_c64().with_(nx=32, ny=32, nz=4, split="LNL")
+    plan = make_plan(wl)
+    a = torch.ones((32, 32), dtype=torch.complex64, device="cuda")
+    b = torch.zeros_like(a)
+    with pytest.raises(ShgError, match="SHG_EUNSUPPORTED"):
+        plan.adjoint(a, b, power_weights=torch.tensor([0.0, 1.0], dtype=torch.float64, device="cuda"))
+    with pytest.raises(ShgError, match="SHG_EUNSUPPORTED"):
+        plan.propagate_heat(a, b)
