@@ -17,11 +17,11 @@ def _timed(fn, reps, torch):
     return (time.perf_counter() - t) / reps
 
 
-def batched(device, reps=3):
+def batched(device, reps=3, split="NLN"):
     import torch
     import workloads
     from paper_2410_04994_amd import Plan, propagate_batch, beams, autotune
-    wls = workloads.c3_batch()
+    wls = [w.with_(split=split) for w in workloads.c3_batch()]
     plans = [Plan(w.params(), "c64") for w in wls]
     autotune.tune_batch(plans)
     a_in = [beams.pump_for(w, dtype=torch.complex64, device=device) for w in wls]
@@ -176,9 +176,38 @@ def self_consistent_loop(device):
             "p_sh_uniform_oven_W": round(float(p_u[1]), 5), "p_sh_self_consistent_W": round(float(p_sc[1]), 5)}
 
 
+def lnl(device, steps=5):
+    """The L/2 - N - L/2 order (one RK4 over dz per step): the 256 x 256 x 1000
+    march and the batched sweep, to compare with the N/2 - L - N/2 lines."""
+    import torch
+    import workloads
+    from paper_2410_04994_amd import Plan, beams, autotune
+    wl = workloads.c2_plain_c64().with_(split="LNL")
+    plan = Plan(wl.params(), "c64")
+    autotune.tune_single(plan)
+    theta = torch.from_numpy(workloads.phase_noise(wl)).to(device)
+    a_in = beams.pump_for(wl, theta=theta, dtype=torch.complex64, device=device)
+    a = torch.empty_like(a_in)
+    b = torch.zeros_like(a_in)
+    ws = plan.workspace(device=device)
+
+    def run():
+        a.copy_(a_in)
+        b.zero_()
+        plan.propagate(a, b, workspace=ws)
+
+    run()
+    sec = _timed(run, steps, torch)
+    out = {"single": {"workload": wl.name + "_lnl", "ms": round(sec * 1e3, 3),
+                      "cell_steps_per_s": round(wl.cell_steps / sec, 1)}}
+    res = batched(device, split="LNL")
+    out["batched"] = {k: res[k] for k in ("ms_per_sweep", "cell_steps_per_s", "frac_hbm_at_64B")}
+    return out
+
+
 def run_all(device) -> dict:
     out = {}
-    for name, fn in (("batched", batched), ("fwd_adj", fwd_adj), ("thermal", thermal),
+    for name, fn in (("batched", batched), ("fwd_adj", fwd_adj), ("lnl", lnl), ("thermal", thermal),
                      ("self_consistent", self_consistent_loop)):
         try:
             out[name] = fn(device)
