@@ -354,6 +354,31 @@ static int fdm_mode(Fdm& f, int axis, const double* mat, const double* x, double
 template <typename R>
 static int solve_direct(Therm& th, const R* heat, R* t_nodes, R* t_mid, char* ws, double* resid_out,
                         hipStream_t st) {
+  {
+    // ovens on both ends of a two-node direction leave no free node: T = T_oven
+    const shg_thermal_params& p = th.p;
+    const int nd[3] = {p.nx, p.ny, p.nz + 1};
+    for (int d = 0; d < 3; ++d) {
+      const int free_nodes = nd[d] - (p.faces[2 * d] == SHG_FACE_OVEN) -
+                             (p.faces[2 * d + 1] == SHG_FACE_OVEN);
+      if (free_nodes <= 0) {
+        const ThermLayout L = therm_layout(th);
+        R* theta = (R*)(ws + L.theta);
+        hipError_t e = hipMemsetAsync(theta, 0, th.g.n * sizeof(R), st);
+        if (e != hipSuccess) return hip_fail(e, "clearing theta");
+        hipLaunchKernelGGL((th_finish<R>), dim3(th.nblk), dim3(256), 0, st, th.g,
+                           (const R*)theta, p.t_oven, t_nodes);
+        if (t_mid) {
+          const size_t plane = (size_t)p.nx * p.ny;
+          hipLaunchKernelGGL((th_midplanes<R>), dim3(th.nblk), dim3(256), 0, st,
+                             (const R*)t_nodes, plane, plane * (size_t)p.nz, t_mid);
+        }
+        if (resid_out) *resid_out = 0.0;
+        e = hipGetLastError();
+        return e == hipSuccess ? SHG_OK : hip_fail(e, "thermal kernel launch");
+      }
+    }
+  }
   int rc = fdm_setup(th, st);
   if (rc) return rc;
   Fdm& f = th.fdm;

@@ -288,3 +288,11 @@ def test_lnl_refuses_adjoint_and_heat_output():
         plan.adjoint(a, b, power_weights=torch.tensor([0.0, 1.0], dtype=torch.float64, device="cuda"))
     with pytest.raises(ShgError, match="SHG_EUNSUPPORTED"):
         plan.propagate_heat(a, b)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_lnl_single_step_and_undepleted(dtype):
+    base = workloads.c2_plain_c64()
+    parity(base.with_(nx=64, ny=64, nz=1, split="LNL"), dtype)
+    parity(base.with_(nx=64, ny=64, nz=30, split="LNL", undepleted=True), dtype)
+    parity(base.with_(nx=128, ny=32, nz=7, split="LNL", lx=base.lx / 2, ly=base.ly / 8), dtype)

@@ -171,3 +171,45 @@ def test_self_consistent_loop(dtype):
         assert out["change"] <= tol_t
         assert np.max(np.abs(got_t - ref_t)) < 2e-3 * rise
         assert rel(out["a_sh"].cpu().numpy(), ref_m["a_sh"]) < 1e-3
+
+
+@pytest.mark.parametrize("method", ["direct", "cg"])
+def test_non_square_grid_and_single_step(method):
+    """64 x 16 nodes per plane and a single z-step (two planes of nodes), with
+    the oven on the x+ face and an insulated z- face."""
+    from paper_2410_04994_amd import Thermal
+    p = dict(nx=64, ny=16, nz=1, lx=1.2e-3, ly=0.3e-3, lcr=0.2e-3)
+    faces = {"x+": "oven", "z-": "insulated"}
+    k_th, h_conv, t_inf, t_oven = 3.0, 5e3, 300.0, 340.0
+    rng = np.random.Generator(np.random.PCG64(23))
+    q = 1e9 * np.exp(rng.normal(size=thermal.grid_shape(p)))
+    ref = thermal.solve(p, thermal.ThermalParams(k_th, h_conv, t_inf, t_oven, faces), q)
+    th = Thermal(p, k_th, h_conv, t_inf, t_oven, faces, "c128", method=method)
+    t, t_mid, it, res = th.solve(torch.from_numpy(q).cuda(), tol=1e-13, max_iter=50000)
+    assert np.max(np.abs(t.cpu().numpy() - ref)) < 1e-9 * np.ptp(ref)
+    assert t_mid.shape == (1, 16, 64)
+
+
+def test_every_node_on_an_oven():
+    """Ovens on both z faces of a single step: no free node, T = T_oven."""
+    from paper_2410_04994_amd import Thermal
+    p = dict(nx=16, ny=16, nz=1, lx=1e-3, ly=1e-3, lcr=1e-4)
+    th = Thermal(p, 5.0, 10.0, 300.0, 330.0, {"z-": "oven", "z+": "oven"}, "c64")
+    q = torch.full(thermal.grid_shape(p), 1e9, dtype=torch.float32, device="cuda")
+    t, t_mid, it, res = th.solve(q)
+    assert torch.all(t == 330.0) and torch.all(t_mid == 330.0)
+
+
+def test_self_consistent_loop_with_cg():
+    from paper_2410_04994_amd import Plan, Thermal, self_consistent
+    p, a0, b0 = field_case(n=16, nz=12, power=30.0, alpha_f=0.5, alpha_sh=3.0, ddk_dT=300.0,
+                           dn_dT=1e-5)
+    k_th, h_conv, t_inf, t_oven = 2.0, 20.0, 295.0, 330.0
+    ref_t, _, _ = thermal.self_consistent(p, oracle_tp("bottom", k_th, h_conv, t_inf, t_oven),
+                                          a0, b0, tol=1e-7)
+    plan = Plan(p, "c128")
+    th = Thermal(p, k_th, h_conv, t_inf, t_oven, presets("bottom"), "c128", method="cg")
+    out = self_consistent(plan, th, torch.from_numpy(a0).cuda(),
+                          torch.zeros(a0.shape, dtype=torch.complex128, device="cuda"),
+                          tol_t=1e-7, solve_tol=1e-13, max_iter=20000)
+    assert np.max(np.abs(out["t_nodes"].cpu().numpy() - ref_t)) < 1e-7 * np.ptp(ref_t)
