@@ -232,6 +232,14 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
   const LdsView<R, 1> b0{&lds[rr][1][0][0]}, b1{&lds[rr][1][1][0]};
   TwRegs<R, N, G> twr;
   tw_load(twr, t, p.tw);
+  // stage coefficients of the uniform-mismatch half-steps, loaded before the
+  // transform so that the phase-table reads overlap it
+  const int stf = p.full ? 2 : 1;
+  HalfStep<R> c2{}, c1{};
+  if constexpr (!TH) {
+    if (p.s_second >= 0) c2 = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);
+    if (p.s_first >= 0) c1 = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, stf);
+  }
   if (p.inv_in) {
     fft_pre<R, N, G, true, 1>(va, a0, a1, t, twr);
     fft_pre<R, N, G, true, 1>(vb, b0, b1, t, twr);
@@ -275,19 +283,16 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
     }
   } else {
     if (p.s_second >= 0) {
-      const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);
 #pragma unroll
-      for (int m = 0; m < E; ++m) rk4_cell(va[m], vb[m], c, p.tf, p.ts, p.h, und);
+      for (int m = 0; m < E; ++m) rk4_cell(va[m], vb[m], c2, p.tf, p.ts, p.h, und);
     }
     if (p.heat) {
 #pragma unroll
       for (int m = 0; m < E; ++m) p.heat[row + t + G * m] = heat_density(va[m], vb[m], p);
     }
     if (p.s_first >= 0) {
-      const int st = p.full ? 2 : 1;
-      const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, st);
 #pragma unroll
-      for (int m = 0; m < E; ++m) rk4_cell(va[m], vb[m], c, p.tf, p.ts, p.h * st, und);
+      for (int m = 0; m < E; ++m) rk4_cell(va[m], vb[m], c1, p.tf, p.ts, p.h * stf, und);
     }
   }
   if (p.fwd_out) {
@@ -370,6 +375,35 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
   cx<R> a, b;
   TwRegs<R, N, G> twr;
   if (fth) tw_load(twr, t, p.tw);
+  // stage coefficients of both half-steps (with a temperature field: of this
+  // cell, from its Psi and samples), formed before the transform so that the
+  // table and field reads overlap it
+  const int stf = p.full ? 2 : 1;
+  HalfStep<R> c2{}, c1{};
+  HalfStepT<R> c2t{}, c1t{};
+  R psi0 = (R)0, psi1 = (R)0, psi2 = (R)0;
+  if constexpr (TH) {
+    const size_t n2 = (size_t)p.ny * N;
+    const R qdz = p.dz * (R)0.25;
+    psi0 = p.psi[idx];
+    psi1 = psi0;
+    if (p.s_second >= 0) {
+      const R dT = p.temp[(size_t)p.s_second * n2 + idx] - p.t_ref;
+      c2t = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, p.ddk, psi0, dT, p.h, qdz,
+                          p.lens_f, p.lens_sh);
+      psi1 += dT * p.dz;
+    }
+    psi2 = psi1;
+    if (p.s_first >= 0) {
+      const R dT = p.temp[(size_t)p.s_first * n2 + idx] - p.t_ref;
+      c1t = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, p.ddk, psi1, dT, (R)0, qdz * stf,
+                          p.lens_f, p.lens_sh, stf);
+      if (p.full) psi2 += dT * p.dz;
+    }
+  } else {
+    if (p.s_second >= 0) c2 = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);
+    if (p.s_first >= 0) c1 = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, stf);
+  }
   if (p.inv_in) {
     if (fth) {
       const cx<R>* src = ff ? p.bin : p.ain;
@@ -394,38 +428,15 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
   }
   const bool und = p.undepleted != 0;
   if constexpr (TH) {
-    const size_t n2 = (size_t)p.ny * N;
-    const R qdz = p.dz * (R)0.25;
-    R psi = p.psi[idx];
-    if (p.tap_psi) p.tap_psi[idx] = psi;
-    if (p.s_second >= 0) {
-      const R dT = p.temp[(size_t)p.s_second * n2 + idx] - p.t_ref;
-      const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, p.ddk, psi,
-                                           dT, p.h, qdz, p.lens_f, p.lens_sh);
-      rk4_cell_t(a, b, c, p.tf, p.ts, p.h, und);
-      psi += dT * p.dz;
-    }
+    if (p.tap_psi) p.tap_psi[idx] = psi0;
+    if (p.s_second >= 0) rk4_cell_t(a, b, c2t, p.tf, p.ts, p.h, und);
     if (p.heat) p.heat[idx] = heat_density(a, b, p);
-    if (p.s_first >= 0) {
-      const R dT = p.temp[(size_t)p.s_first * n2 + idx] - p.t_ref;
-      const int st = p.full ? 2 : 1;
-      const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, p.ddk, psi, dT,
-                                           (R)0, qdz * st, p.lens_f, p.lens_sh, st);
-      rk4_cell_t(a, b, c, p.tf, p.ts, p.h * st, und);
-      if (p.full) psi += dT * p.dz;
-    }
-    if (p.s_second >= 0 || (p.full && p.s_first >= 0)) p.psi[idx] = psi;
+    if (p.s_first >= 0) rk4_cell_t(a, b, c1t, p.tf, p.ts, p.h * stf, und);
+    if (p.s_second >= 0 || (p.full && p.s_first >= 0)) p.psi[idx] = psi2;
   } else {
-    if (p.s_second >= 0) {
-      const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);
-      rk4_cell(a, b, c, p.tf, p.ts, p.h, und);
-    }
+    if (p.s_second >= 0) rk4_cell(a, b, c2, p.tf, p.ts, p.h, und);
     if (p.heat) p.heat[idx] = heat_density(a, b, p);
-    if (p.s_first >= 0) {
-      const int st = p.full ? 2 : 1;
-      const HalfStep<R> c = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, st);
-      rk4_cell(a, b, c, p.tf, p.ts, p.h * st, und);
-    }
+    if (p.s_first >= 0) rk4_cell(a, b, c1, p.tf, p.ts, p.h * stf, und);
   }
   if (p.fwd_out) {
     __syncthreads();   // every thread has read its cell before it is overwritten
@@ -496,23 +507,28 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& p) {
   cx<R> v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = col[(size_t)(t + G * m) * p.nx];
-  const LdsView<R, TC> b0{&lds[0][c]}, b1{&lds[1][c]};
-  TwRegs<R, N, G> twr;
-  tw_load(twr, t, p.tw);
-  fft_pre<R, N, G, false, TC>(v, b0, b1, t, twr);
-  // diffraction + linear loss (Eq. A.4), product formed in FP64
+  // diffraction + linear loss (Eq. A.4): the FP64 product m_x m_y of this
+  // thread's bins, formed before the transforms so that its loads overlap FFT_y
   const double* __restrict__ mxp = p.mx[field];
   const double* __restrict__ myp = p.my[field];
   const double sgn = p.conj_prop ? -1.0 : 1.0;
   const double mxr = mxp[2 * x], mxi = sgn * mxp[2 * x + 1];
+  double mr[E], mi[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int qy = t + G * m;
     const double myr = myp[2 * qy], myi = sgn * myp[2 * qy + 1];
-    const double mr = mxr * myr - mxi * myi;
-    const double mi = mxr * myi + mxi * myr;
+    mr[m] = mxr * myr - mxi * myi;
+    mi[m] = mxr * myi + mxi * myr;
+  }
+  const LdsView<R, TC> b0{&lds[0][c]}, b1{&lds[1][c]};
+  TwRegs<R, N, G> twr;
+  tw_load(twr, t, p.tw);
+  fft_pre<R, N, G, false, TC>(v, b0, b1, t, twr);
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
     const double vr = (double)v[m].re, vi = (double)v[m].im;
-    v[m] = {(R)(vr * mr - vi * mi), (R)(vr * mi + vi * mr)};
+    v[m] = {(R)(vr * mr[m] - vi * mi[m]), (R)(vr * mi[m] + vi * mr[m])};
   }
   fft_pre<R, N, G, true, TC>(v, b0, b1, t, twr);
 #pragma unroll
