@@ -303,22 +303,49 @@ struct RowAdjTArgs {
 
 // Pull-back of one cell through the first half-step of s_first and the second
 // half-step of s_second (either may be absent), from the staged forward state.
+// Per-cell inputs of the adjoint row pass that do not depend on the
+// cotangent: the staged forward state, the stage coefficients and, with a
+// temperature field, Psi, the carry and the two samples.  Loading them before
+// the cotangent's transform lets their latency overlap it.
+template <typename R, bool TH>
+struct AdjPre {
+  cx<R> ua, ub;
+  HalfStep<R> c1, c2;
+  R psi, dT2, dT1;
+  Carry<R> cr;
+};
+
+template <typename R, bool TH>
+__device__ __forceinline__ AdjPre<R, TH> adj_load(const RowAdjArgs<R>& p, const RowAdjTArgs<R>& q,
+                                                  size_t idx, size_t n2) {
+  AdjPre<R, TH> a{};
+  a.ua = p.ua[idx];
+  a.ub = p.ub[idx];
+  if constexpr (!TH) {
+    if (p.s_first >= 0) a.c1 = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks);
+    if (p.s_second >= 0) a.c2 = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);
+  } else {
+    a.psi = q.psi[idx];
+    a.cr = q.carry[idx];
+    if (p.s_second >= 0) a.dT2 = q.temp[(size_t)p.s_second * n2 + idx] - q.t_ref;
+    if (p.s_first >= 0) a.dT1 = q.temp[(size_t)p.s_first * n2 + idx] - q.t_ref;
+  }
+  return a;
+}
+
 template <typename R, bool TH>
 __device__ __forceinline__ void adj_cell(const RowAdjArgs<R>& p, const RowAdjTArgs<R>& q,
-                                         size_t idx, size_t n2, cx<R>& la, cx<R>& lb,
-                                         double (&acc)[4]) {
+                                         const AdjPre<R, TH>& pre, size_t idx, cx<R>& la,
+                                         cx<R>& lb, double (&acc)[4]) {
   const bool und = p.undepleted != 0;
   const R h = p.h;
-  const cx<R> ua = p.ua[idx];
-  const cx<R> ub = p.ub[idx];
+  const cx<R> ua = pre.ua;
+  const cx<R> ub = pre.ub;
   cx<R> ya = ua, yb = ub;
   if constexpr (!TH) {
-    HalfStep<R> c1{}, c2{};
-    if (p.s_first >= 0) c1 = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks);
-    if (p.s_second >= 0) {
-      c2 = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);
-      rk4_cell(ya, yb, c2, p.tf, p.ts, h, und);
-    }
+    const HalfStep<R>& c1 = pre.c1;
+    const HalfStep<R>& c2 = pre.c2;
+    if (p.s_second >= 0) rk4_cell(ya, yb, c2, p.tf, p.ts, h, und);
     R g = 0, gt = 0;
     if (p.s_first >= 0) {
       rk4_vjp(ya, yb, la, lb, c1, p.tf, p.ts, h, und, (R)0, g, gt);
@@ -334,18 +361,18 @@ __device__ __forceinline__ void adj_cell(const RowAdjArgs<R>& p, const RowAdjTAr
     }
   } else {
     const R qdz = q.dz * (R)0.25;
-    R psi = q.psi[idx];
-    Carry<R> cr = q.carry[idx];
+    R psi = pre.psi;
+    Carry<R> cr = pre.cr;
     HalfStepT<R> c2{};
     if (p.s_second >= 0) {
-      const R dT = q.temp[(size_t)p.s_second * n2 + idx] - q.t_ref;
+      const R dT = pre.dT2;
       c2 = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, q.ddk, psi, dT, h, qdz,
                          q.lens_f, q.lens_sh);
       rk4_cell_t(ya, yb, c2, p.tf, p.ts, h, und);
       psi += dT * q.dz;
     }
     if (p.s_first >= 0) {
-      const R dT = q.temp[(size_t)p.s_first * n2 + idx] - q.t_ref;
+      const R dT = pre.dT1;
       const HalfStepT<R> c1 = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, q.ddk, psi, dT,
                                             (R)0, qdz, q.lens_f, q.lens_sh);
       R g = 0, gt = 0, gl = 0;
@@ -373,6 +400,13 @@ __device__ __forceinline__ void adj_cell(const RowAdjArgs<R>& p, const RowAdjTAr
     }
     q.carry[idx] = cr;
   }
+}
+
+template <typename R, bool TH>
+__device__ __forceinline__ void adj_cell(const RowAdjArgs<R>& p, const RowAdjTArgs<R>& q,
+                                         size_t idx, size_t n2, cx<R>& la, cx<R>& lb,
+                                         double (&acc)[4]) {
+  adj_cell<R, TH>(p, q, adj_load<R, TH>(p, q, idx, n2), idx, la, lb, acc);
 }
 
 template <typename R, int T>
@@ -463,6 +497,7 @@ __global__ void __launch_bounds__(WideShape<N>::threads) row_adj_pass_wide(RowAd
   cx<R> la, lb;
   TwRegs<R, N, G> twr;
   if (fth) tw_load(twr, t, p.tw);
+  const AdjPre<R, TH> pre = adj_load<R, TH>(p, q, idx, n2);
   if (p.inv_in) {
     if (fth) {
       const cx<R>* src = ff ? p.lb : p.la;
@@ -482,7 +517,7 @@ __global__ void __launch_bounds__(WideShape<N>::threads) row_adj_pass_wide(RowAd
     lb = p.lb[idx];
   }
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  adj_cell<R, TH>(p, q, idx, n2, la, lb, acc);
+  adj_cell<R, TH>(p, q, pre, idx, la, lb, acc);
   if (p.fwd_out) {
     __syncthreads();
     cell[0][cr][pad16(cxi)] = la;
