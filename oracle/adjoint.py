@@ -203,7 +203,7 @@ def adjoint(p: dict, a_f0: np.ndarray, a_sh0: np.ndarray, g_f_out: np.ndarray,
         acc_phi = acc_phi + g_phi_s
         g_dk_cells.append(g_dk_s)
         if temp is not None:
-            g_temp[s] = p["ddk_dT"] * g_dk_s + (gT1 + gT2)
+            g_temp[s] = ssfm.thermal_mismatch_slope(p, dT) * g_dk_s + (gT1 + gT2)
     g_dk_cells.reverse()
     g_dk = np.array([float(np.sum(g)) for g in g_dk_cells])
     out = {

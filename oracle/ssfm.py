@@ -22,9 +22,10 @@ the design notes and pinned by a test in tests/test_oracle_pins.py):
   * the accumulated mismatch phase phi(z) = int_0^z dk dz' (Eq. 3) is exact for
     a mismatch that is constant within each z-step (per step, or per cell when
     a temperature field is given).
-  * temperature (optional): dk = dk_s + (d dk/dT)(T - T_ref) per cell, and a
-    thermal-lens term -i (2 pi/lambda_j)(dn/dT)(T - T_ref) A_j, with T sampled
-    at the step mid-plane.
+  * temperature (optional): dk = dk_s + c1 dT + c2 dT^2 + c3 dT^3 per cell,
+    dT = T - T_ref (c1 = d dk/dT; c2, c3 optional, a polynomial stand-in for the
+    full dk(T) of Eq. 4), and a thermal-lens term -i (2 pi/lambda_j)(dn/dT) dT
+    A_j, with T sampled at the step mid-plane.
   * undepleted pump (Sec. 5.1): the nonlinear part of dA_F/dz is zero.
   * spatial walk-off (optional; Sec. 4, the propagator set-up of the package
     description): dA_j/dz gains -tan(rho_j) dA_j/dx, a linear term that moves the
@@ -106,6 +107,20 @@ def propagator(p: dict, k: float, alpha: float, dz: float, walkoff: float = 0.0)
     return np.exp((2j * math.pi ** 2 * q2 / k - alpha / 2.0 - drift) * dz)
 
 
+def thermal_mismatch(p: dict, dT):
+    """dk(T) - dk(T_ref) = c1 dT + c2 dT^2 + c3 dT^3 per cell (c1 = "ddk_dT",
+    c2 = "ddk_dT2", c3 = "ddk_dT3"; the quadratic and cubic terms stand in for
+    the Sellmeier and grating-period temperature dependence of Eq. 4)."""
+    c2, c3 = p.get("ddk_dT2", 0.0), p.get("ddk_dT3", 0.0)
+    return dT * (p["ddk_dT"] + dT * (c2 + dT * c3))
+
+
+def thermal_mismatch_slope(p: dict, dT):
+    """d(dk)/dT at the cell's temperature."""
+    c2, c3 = p.get("ddk_dT2", 0.0), p.get("ddk_dT3", 0.0)
+    return p["ddk_dT"] + dT * (2.0 * c2 + 3.0 * c3 * dT)
+
+
 def split_order(p: dict) -> str:
     """"NLN" (N/2 - L - N/2, default) or "LNL" (L/2 - N - L/2)."""
     order = p.get("split", "NLN")
@@ -164,7 +179,7 @@ def step_mismatch(p: dict, s: int, dk_z: Optional[np.ndarray], temp: Optional[np
     if temp is None:
         return base, None
     dT = np.asarray(temp[s], dtype=np.float64) - p["t_ref"]
-    return base + p["ddk_dT"] * dT, dT
+    return base + thermal_mismatch(p, dT), dT
 
 
 def power(a: np.ndarray, n: float, dx: float, dy: float) -> float:

@@ -36,10 +36,13 @@ def loss(p, a, b, g_f, g_sh, w, dk_z=None, temp=None):
             + w[0] * out["p_f"] + w[1] * out["p_sh"])
 
 
-@pytest.mark.parametrize("with_temp,undepleted,walkoff", [(False, False, 0.0), (True, False, 0.0),
-                                                          (True, True, 0.0), (False, False, 0.02)])
-def test_adjoint_matches_central_differences(with_temp, undepleted, walkoff):
+@pytest.mark.parametrize("with_temp,undepleted,walkoff,cubic", [
+    (False, False, 0.0, False), (True, False, 0.0, False), (True, True, 0.0, False),
+    (False, False, 0.02, False), (True, False, 0.0, True)])
+def test_adjoint_matches_central_differences(with_temp, undepleted, walkoff, cubic):
     p = params(undepleted=undepleted, walkoff_sh=walkoff, walkoff_f=-0.5 * walkoff)
+    if cubic:
+        p.update(ddk_dT2=-120.0, ddk_dT3=45.0)
     r = rng(21)
     shape = (p["ny"], p["nx"])
     a = crand(r, shape, 5e7)

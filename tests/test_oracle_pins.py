@@ -334,7 +334,8 @@ def brute_force_march(p, a, b, temp=None):
         for j in range(ny):
             for i in range(nx):
                 dT = 0.0 if temp is None else temp[s][j][i] - p["t_ref"]
-                dk = p["dk0"] + p["ddk_dT"] * dT
+                dk = (p["dk0"] + p["ddk_dT"] * dT + p.get("ddk_dT2", 0.0) * dT ** 2
+                      + p.get("ddk_dT3", 0.0) * dT ** 3)
 
                 def f(t, u, v):
                     ph = phi[j, i] + dk * t
@@ -356,7 +357,8 @@ def brute_force_march(p, a, b, temp=None):
         for j in range(ny):
             for i in range(nx):
                 dT = 0.0 if temp is None else temp[s][j][i] - p["t_ref"]
-                dk = p["dk0"] + p["ddk_dT"] * dT
+                dk = (p["dk0"] + p["ddk_dT"] * dT + p.get("ddk_dT2", 0.0) * dT ** 2
+                      + p.get("ddk_dT3", 0.0) * dT ** 3)
 
                 def f(t, u, v):
                     ph = phi[j, i] + dk * t
@@ -377,11 +379,14 @@ def brute_force_march(p, a, b, temp=None):
     return a, b
 
 
-@pytest.mark.parametrize("shape,with_temp", [((4, 4), False), ((8, 4), False), ((4, 8), True)])
-def test_tiny_grid_brute_force(shape, with_temp):
+@pytest.mark.parametrize("shape,with_temp,cubic", [((4, 4), False, False), ((8, 4), False, False),
+                                                  ((4, 8), True, False), ((4, 4), True, True)])
+def test_tiny_grid_brute_force(shape, with_temp, cubic):
     ny, nx = shape
     p = base_params(n=4, nz=3, width=0.05e-3, lcr=1e-3, dk0=500.0, alpha_f=3.0, alpha_sh=5.0,
                     beta_f=1e-11, beta_sh=2e-11, ddk_dT=40.0, dn_dT=2e-4, t_ref=300.0)
+    if cubic:
+        p.update(ddk_dT2=-150.0, ddk_dT3=60.0)
     p.update(nx=nx, ny=ny, lx=0.05e-3 * nx / 4, ly=0.05e-3 * ny / 4)
     rng = np.random.Generator(np.random.PCG64(17))
     a = (rng.normal(size=shape) + 1j * rng.normal(size=shape)) * 4e7
@@ -394,6 +399,32 @@ def test_tiny_grid_brute_force(shape, with_temp):
     # the nonlinear terms matter at this amplitude
     lin = ssfm.propagate(dict(p, d_eff=0.0, beta_f=0.0, beta_sh=0.0), a, b, temp=temp)
     assert rel(lin["a_sh"], bb) > 1e-3
+
+
+@pytest.mark.parametrize("dT", [-1.5, 0.8, 2.6])
+def test_polynomial_mismatch_with_uniform_offset_equals_shifted_dk0(dT):
+    """A uniform temperature offset with no thermal lens (dn/dT = 0) only moves
+    the phase mismatch, so the march with the cubic dk(T) must equal the
+    temperature-free march at dk0 + c1 dT + c2 dT^2 + c3 dT^3.  The third case
+    is chosen so that the shift cancels dk0 (phase matching restored by
+    temperature tuning): there P_SH must reach the dk = 0 value, far above the
+    mismatched one."""
+    lcr, xi = 10e-3, 1.0
+    w0 = waist(lcr, xi)
+    c1, c2, c3 = 3000.0, -40.0, 9.0
+    dk0 = -(c1 * 2.6 + c2 * 2.6 ** 2 + c3 * 2.6 ** 3)
+    p = base_params(n=32, nz=40, lcr=lcr, width=10 * w0, dk0=dk0, alpha_f=2.0, alpha_sh=4.0,
+                    ddk_dT=c1, ddk_dT2=c2, ddk_dT3=c3, dn_dT=0.0, t_ref=300.0)
+    a0 = beams.input_pump(p, 200.0, w0, lcr / 2)
+    out = ssfm.propagate(p, a0, np.zeros_like(a0), temp=np.full((40, 32, 32), 300.0 + dT))
+    shifted = dict(p, dk0=dk0 + c1 * dT + c2 * dT * dT + c3 * dT * dT * dT)
+    ref = ssfm.propagate(shifted, a0, np.zeros_like(a0))
+    assert rel(out["a_f"], ref["a_f"]) < 1e-12
+    assert rel(out["a_sh"], ref["a_sh"]) < 1e-12
+    if dT == 2.6:
+        mismatched = ssfm.propagate(p, a0, np.zeros_like(a0))
+        assert abs(shifted["dk0"]) < 1e-9
+        assert out["p_sh"] > 20.0 * mismatched["p_sh"]
 
 
 def test_resume_from_midpoint():

@@ -59,6 +59,8 @@ class Workload:
     beta_sh: float = 0.0
     dk0: float = 0.0
     ddk_dT: float = 0.0
+    ddk_dT2: float = 0.0           # d2(dk)/dT2 / 2 [rad/(m K^2)]
+    ddk_dT3: float = 0.0           # d3(dk)/dT3 / 6 [rad/(m K^3)]
     dn_dT: float = 0.0
     t_ref: float = 0.0
     walkoff_f: float = 0.0         # spatial walk-off angle of the fundamental [rad]
@@ -74,7 +76,7 @@ class Workload:
     def params(self) -> dict:
         """Plain parameter dict understood by both the oracle and the binding."""
         keys = ("nx", "ny", "nz", "lx", "ly", "lcr", "lambda_f", "n_f", "n_sh", "d_eff",
-                "alpha_f", "alpha_sh", "beta_f", "beta_sh", "dk0", "ddk_dT", "dn_dT",
+                "alpha_f", "alpha_sh", "beta_f", "beta_sh", "dk0", "ddk_dT", "ddk_dT2", "ddk_dT3", "dn_dT",
                 "t_ref", "walkoff_f", "walkoff_sh", "split", "undepleted")
         return {k: getattr(self, k) for k in keys}
 
