@@ -22,10 +22,11 @@ the design notes and pinned by a test in tests/test_oracle_pins.py):
   * the accumulated mismatch phase phi(z) = int_0^z dk dz' (Eq. 3) is exact for
     a mismatch that is constant within each z-step (per step, or per cell when
     a temperature field is given).
-  * temperature (optional): dk = dk_s + c1 dT + c2 dT^2 + c3 dT^3 per cell,
-    dT = T - T_ref (c1 = d dk/dT; c2, c3 optional, a polynomial stand-in for the
-    full dk(T) of Eq. 4), and a thermal-lens term -i (2 pi/lambda_j)(dn/dT) dT
-    A_j, with T sampled at the step mid-plane.
+  * temperature (optional): dk = dk_s + [dk(T) - dk(T_ref)] per cell, dk(T)
+    of Eq. 4 with a cubic in dT = T - T_ref standing in for the Sellmeier part
+    and the printed grating period Lambda(T) (see thermal_mismatch), and a
+    thermal-lens term -i (2 pi/lambda_j)(dn/dT) dT A_j, with T sampled at the
+    step mid-plane.
   * undepleted pump (Sec. 5.1): the nonlinear part of dA_F/dz is zero.
   * spatial walk-off (optional; Sec. 4, the propagator set-up of the package
     description): dA_j/dz gains -tan(rho_j) dA_j/dx, a linear term that moves the
@@ -107,18 +108,41 @@ def propagator(p: dict, k: float, alpha: float, dz: float, walkoff: float = 0.0)
     return np.exp((2j * math.pi ** 2 * q2 / k - alpha / 2.0 - drift) * dz)
 
 
+T_25C = 298.15    # the reference temperature of the grating-period expansion (Eq. 4)
+
+
+def grating_period(p: dict, T):
+    """Lambda(T) = Lambda(25 C) [1 + a (T - 25 C) + b (T - 25 C)^2] (Eq. 4)."""
+    d = T - T_25C
+    return p["grating_period"] * (1.0 + p.get("grating_a", 0.0) * d + p.get("grating_b", 0.0) * d * d)
+
+
 def thermal_mismatch(p: dict, dT):
-    """dk(T) - dk(T_ref) = c1 dT + c2 dT^2 + c3 dT^3 per cell (c1 = "ddk_dT",
-    c2 = "ddk_dT2", c3 = "ddk_dT3"; the quadratic and cubic terms stand in for
-    the Sellmeier and grating-period temperature dependence of Eq. 4)."""
+    """dk(T) - dk(T_ref) per cell, dT = T - T_ref, following Eq. 4:
+      dispersion part (4 pi/lambda_F)(n_SH(T) - n_F(T)): c1 dT + c2 dT^2 + c3 dT^3
+        (c1 = "ddk_dT", c2 = "ddk_dT2", c3 = "ddk_dT3"), a polynomial stand-in
+        for the Sellmeier indices, which the paper only cites;
+      grating part -2 pi / Lambda(T): exactly as printed, with Lambda(25 C) =
+        "grating_period" (0 = no grating term), a = "grating_a", b = "grating_b"."""
     c2, c3 = p.get("ddk_dT2", 0.0), p.get("ddk_dT3", 0.0)
-    return dT * (p["ddk_dT"] + dT * (c2 + dT * c3))
+    out = dT * (p["ddk_dT"] + dT * (c2 + dT * c3))
+    if p.get("grating_period", 0.0) > 0.0:
+        t_ref = p["t_ref"]
+        out = out + (2.0 * math.pi / grating_period(p, t_ref)
+                     - 2.0 * math.pi / grating_period(p, t_ref + dT))
+    return out
 
 
 def thermal_mismatch_slope(p: dict, dT):
     """d(dk)/dT at the cell's temperature."""
     c2, c3 = p.get("ddk_dT2", 0.0), p.get("ddk_dT3", 0.0)
-    return p["ddk_dT"] + dT * (2.0 * c2 + 3.0 * c3 * dT)
+    out = p["ddk_dT"] + dT * (2.0 * c2 + 3.0 * c3 * dT)
+    if p.get("grating_period", 0.0) > 0.0:
+        T = p["t_ref"] + dT
+        lam = grating_period(p, T)
+        dlam = p["grating_period"] * (p.get("grating_a", 0.0) + 2.0 * p.get("grating_b", 0.0) * (T - T_25C))
+        out = out + 2.0 * math.pi * dlam / (lam * lam)
+    return out
 
 
 def split_order(p: dict) -> str:

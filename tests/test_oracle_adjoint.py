@@ -42,7 +42,8 @@ def loss(p, a, b, g_f, g_sh, w, dk_z=None, temp=None):
 def test_adjoint_matches_central_differences(with_temp, undepleted, walkoff, cubic):
     p = params(undepleted=undepleted, walkoff_sh=walkoff, walkoff_f=-0.5 * walkoff)
     if cubic:
-        p.update(ddk_dT2=-120.0, ddk_dT3=45.0)
+        # cubic dispersion part and a grating period with an exaggerated expansion
+        p.update(ddk_dT2=-120.0, ddk_dT3=45.0, grating_period=8e-6, grating_a=2e-3, grating_b=-4e-5)
     r = rng(21)
     shape = (p["ny"], p["nx"])
     a = crand(r, shape, 5e7)

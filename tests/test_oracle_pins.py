@@ -12,6 +12,7 @@ import os
 import numpy as np
 import pytest
 
+import workloads
 from oracle import ssfm, beams, pins
 
 LAM = 1064e-9
@@ -401,8 +402,34 @@ def test_tiny_grid_brute_force(shape, with_temp, cubic):
     assert rel(lin["a_sh"], bb) > 1e-3
 
 
-@pytest.mark.parametrize("dT", [-1.5, 0.8, 2.6])
-def test_polynomial_mismatch_with_uniform_offset_equals_shifted_dk0(dT):
+def test_grating_term_derivatives_at_25C_match_the_expansion():
+    """-2 pi/Lambda(T) with Lambda = Lambda25 (1 + a u + b u^2), u = T - 25 C,
+    has first derivative (2 pi/Lambda25) a and second derivative
+    (2 pi/Lambda25)(2 b - 2 a^2) at u = 0 (calculus on Eq. 4).  The oracle's
+    mismatch shift is checked by differences against both, with T_ref away
+    from 25 C so that a wrong reference temperature fails, and its slope
+    against differences of the shift over a range of temperatures."""
+    a, b, lam = workloads.GRATING_A, workloads.GRATING_B, workloads.GRATING_PERIOD
+    p = dict(ddk_dT=0.0, grating_period=lam, grating_a=a, grating_b=b, t_ref=330.0)
+    g = 2 * math.pi / lam
+    h = 0.5
+    dT25 = ssfm.T_25C - p["t_ref"]
+    f = lambda x: ssfm.thermal_mismatch(p, dT25 + x)
+    d1 = (f(h) - f(-h)) / (2 * h)
+    d2 = (f(h) - 2 * f(0.0) + f(-h)) / (h * h)
+    assert abs(d1 / (g * a) - 1) < 1e-6
+    assert abs(d2 / (g * (2 * b - 2 * a * a)) - 1) < 1e-4
+    assert ssfm.thermal_mismatch(p, 3.0) > 0.0       # heating lengthens the period
+    pc = dict(p, ddk_dT=40.0, ddk_dT2=-3.0, ddk_dT3=0.7)
+    for dT in (-20.0, -1.0, 0.0, 2.5, 30.0):
+        e = 1e-3
+        fd = (ssfm.thermal_mismatch(pc, dT + e) - ssfm.thermal_mismatch(pc, dT - e)) / (2 * e)
+        assert abs(fd - ssfm.thermal_mismatch_slope(pc, dT)) < 1e-6 * abs(fd)
+    assert ssfm.thermal_mismatch(pc, 0.0) == 0.0
+
+
+@pytest.mark.parametrize("dT,grating", [(-1.5, False), (0.8, False), (2.6, False), (2.6, True)])
+def test_polynomial_mismatch_with_uniform_offset_equals_shifted_dk0(dT, grating):
     """A uniform temperature offset with no thermal lens (dn/dT = 0) only moves
     the phase mismatch, so the march with the cubic dk(T) must equal the
     temperature-free march at dk0 + c1 dT + c2 dT^2 + c3 dT^3.  The third case
@@ -412,12 +439,21 @@ def test_polynomial_mismatch_with_uniform_offset_equals_shifted_dk0(dT):
     lcr, xi = 10e-3, 1.0
     w0 = waist(lcr, xi)
     c1, c2, c3 = 3000.0, -40.0, 9.0
-    dk0 = -(c1 * 2.6 + c2 * 2.6 ** 2 + c3 * 2.6 ** 3)
+    shift = lambda x: c1 * x + c2 * x * x + c3 * x * x * x
+    extra = {}
+    if grating:
+        # a period 1 % too short at 25 C, tuned by temperature; the expansion
+        # coefficients are scaled up so that the grating term dominates
+        lam25, a, b = 8e-6, 3e-3, -2e-5
+        extra = dict(grating_period=lam25, grating_a=a, grating_b=b)
+        period = lambda T: lam25 * (1 + a * (T - 298.15) + b * (T - 298.15) ** 2)
+        shift = lambda x, s0=shift: s0(x) + 2 * math.pi / period(300.0) - 2 * math.pi / period(300.0 + x)
+    dk0 = -shift(2.6)
     p = base_params(n=32, nz=40, lcr=lcr, width=10 * w0, dk0=dk0, alpha_f=2.0, alpha_sh=4.0,
-                    ddk_dT=c1, ddk_dT2=c2, ddk_dT3=c3, dn_dT=0.0, t_ref=300.0)
+                    ddk_dT=c1, ddk_dT2=c2, ddk_dT3=c3, dn_dT=0.0, t_ref=300.0, **extra)
     a0 = beams.input_pump(p, 200.0, w0, lcr / 2)
     out = ssfm.propagate(p, a0, np.zeros_like(a0), temp=np.full((40, 32, 32), 300.0 + dT))
-    shifted = dict(p, dk0=dk0 + c1 * dT + c2 * dT * dT + c3 * dT * dT * dT)
+    shifted = dict(p, dk0=dk0 + shift(dT))
     ref = ssfm.propagate(shifted, a0, np.zeros_like(a0))
     assert rel(out["a_f"], ref["a_f"]) < 1e-12
     assert rel(out["a_sh"], ref["a_sh"]) < 1e-12

@@ -31,6 +31,10 @@ ALPHA_F = 0.05          # 0.0005 /cm  -> 1/m (intensity absorption)
 ALPHA_SH = 0.2          # 0.002 /cm   -> 1/m
 BETA_TPA = 1e-12        # 0.1 cm/GW   -> m/W (two-photon absorption)
 T_OVEN = 329.65         # 56.5 C, the oven temperature of the paper's Example 1 [K]
+GRATING_A = 2.2e-6      # thermal expansion of the MgO:sPPLT poling period, Eq. 4 [1/K]
+GRATING_B = -5.9e-9     # [1/K^2]
+GRATING_PERIOD = 7.97e-6  # first-order period for 1064 -> 532 nm in PPLT at 25 C [m]; a
+                          # stand-in, the paper gives no value
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -61,6 +65,9 @@ class Workload:
     ddk_dT: float = 0.0
     ddk_dT2: float = 0.0           # d2(dk)/dT2 / 2 [rad/(m K^2)]
     ddk_dT3: float = 0.0           # d3(dk)/dT3 / 6 [rad/(m K^3)]
+    grating_period: float = 0.0    # poling period at 25 C [m]; 0 = no grating term in dk(T)
+    grating_a: float = 0.0         # linear thermal expansion of the period [1/K]
+    grating_b: float = 0.0         # quadratic thermal expansion of the period [1/K^2]
     dn_dT: float = 0.0
     t_ref: float = 0.0
     walkoff_f: float = 0.0         # spatial walk-off angle of the fundamental [rad]
@@ -76,7 +83,7 @@ class Workload:
     def params(self) -> dict:
         """Plain parameter dict understood by both the oracle and the binding."""
         keys = ("nx", "ny", "nz", "lx", "ly", "lcr", "lambda_f", "n_f", "n_sh", "d_eff",
-                "alpha_f", "alpha_sh", "beta_f", "beta_sh", "dk0", "ddk_dT", "ddk_dT2", "ddk_dT3", "dn_dT",
+                "alpha_f", "alpha_sh", "beta_f", "beta_sh", "dk0", "ddk_dT", "ddk_dT2", "ddk_dT3", "grating_period", "grating_a", "grating_b", "dn_dT",
                 "t_ref", "walkoff_f", "walkoff_sh", "split", "undepleted")
         return {k: getattr(self, k) for k in keys}
 
