@@ -14,9 +14,14 @@
  *     conservation with I = eps0 c n |A|^2 / 2 of Sec. 2.2);
  *   - two-photon absorption acts on intensity, beta~_j = beta_j eps0 c n_j / 2;
  *   - the linear loss alpha_j is exact inside the Fourier-space propagator;
- *   - with a temperature field, dk = dk_s + ddk_dT (T - t_ref) per cell and a
- *     thermal-lens term -i (2 pi / lambda_j) dn_dT (T - t_ref) A_j, with T given
- *     at each step's mid-plane;
+ *   - with a temperature field, dk = dk_s + dk(T) - dk(T_ref) per cell, dk(T)
+ *     of Eq. 4: its dispersion part (4 pi/lambda_F)(n_SH - n_F) as the cubic
+ *     c1 dT + c2 dT^2 + c3 dT^3, dT = T - t_ref, (c1, c2, c3) = (ddk_dT,
+ *     ddk_dT2, ddk_dT3), a stand-in for the Sellmeier indices the paper only
+ *     cites; its grating part -2 pi / Lambda(T) as printed, Lambda(T) =
+ *     grating_period [1 + grating_a (T - 25 C) + grating_b (T - 25 C)^2]; and
+ *     a thermal-lens term -i (2 pi / lambda_j) dn_dT dT A_j, with T given at
+ *     each step's mid-plane;
  *   - SHG_UNDEPLETED zeroes the whole nonlinear part of dA_F/dz (Sec. 5.1);
  *   - spatial walk-off (the tan(rho) dA/dx term of the package's propagators,
  *     Sec. 4): dA_j/dz gains -tan(rho_j) dA_j/dx, which moves wave j towards +x
@@ -93,6 +98,13 @@ typedef struct {
                             /* K = nz when nz staged steps fit in 4 GiB)       */
   double walkoff_f, walkoff_sh; /* spatial walk-off angles rho_F, rho_SH [rad], */
                             /* |rho| < pi/2; 0 for quasi-phase matching        */
+  double ddk_dT2, ddk_dT3;  /* quadratic and cubic terms of dk(T) [rad/(m K^2)],*/
+                            /* [rad/(m K^3)]; temperature field only, 0 = linear */
+  double grating_period;    /* poling period Lambda at 25 C [m], temperature    */
+                            /* field only; 0 = no grating term in dk(T)         */
+  double grating_a, grating_b; /* thermal expansion of Lambda [1/K], [1/K^2]    */
+                            /* about 25 C (2.2e-6, -5.9e-9 for MgO:sPPLT); the  */
+                            /* period must stay positive over the field's T     */
 } shg_params;
 
 /* Create a plan: validates the parameters, builds the FP64 propagator and
@@ -101,7 +113,8 @@ typedef struct {
  * device tables on the current HIP device.
  * Errors: SHG_EINVAL (NULL pointer, nx/ny not a power of two in [16, 512],
  * nz < 1, non-positive or non-finite lengths/indices/wavelength, negative
- * absorption, |walk-off| >= pi/2), SHG_ENOMEM, SHG_EDEVICE.  *out is NULL on
+ * absorption, non-finite dk coefficients, negative grating period or one
+ * that is not positive at t_ref, |walk-off| >= pi/2), SHG_ENOMEM, SHG_EDEVICE.  *out is NULL on
  * error. */
 int shg_plan_create(shg_plan **out, const shg_params *p, shg_dtype dtype);
 

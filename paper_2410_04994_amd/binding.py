@@ -38,7 +38,9 @@ class ShgParams(ctypes.Structure):
                 ("beta_sh", ctypes.c_double), ("dk0", ctypes.c_double), ("ddk_dT", ctypes.c_double),
                 ("dn_dT", ctypes.c_double), ("t_ref", ctypes.c_double), ("flags", ctypes.c_uint32),
                 ("checkpoint_every", ctypes.c_int32), ("walkoff_f", ctypes.c_double),
-                ("walkoff_sh", ctypes.c_double)]
+                ("walkoff_sh", ctypes.c_double), ("ddk_dT2", ctypes.c_double),
+                ("ddk_dT3", ctypes.c_double), ("grating_period", ctypes.c_double),
+                ("grating_a", ctypes.c_double), ("grating_b", ctypes.c_double)]
 
 
 SHG_FACE_AIR, SHG_FACE_OVEN, SHG_FACE_INSULATED = 0, 1, 2
@@ -137,7 +139,7 @@ def _stream(stream=None):
 
 PARAM_KEYS = ("nx", "ny", "nz", "lx", "ly", "lcr", "lambda_f", "n_f", "n_sh", "d_eff", "alpha_f",
               "alpha_sh", "beta_f", "beta_sh", "dk0", "ddk_dT", "dn_dT", "t_ref", "walkoff_f",
-              "walkoff_sh")
+              "walkoff_sh", "ddk_dT2", "ddk_dT3", "grating_period", "grating_a", "grating_b")
 
 
 def make_params(params: dict, flags: int = 0, checkpoint_every: int = 0) -> ShgParams:

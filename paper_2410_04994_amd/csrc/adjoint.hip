@@ -184,6 +184,8 @@ static int adjoint_t(Plan& pl, const void* a_f_in, const void* a_sh_in, const do
   const unsigned nb = (unsigned)((n2 + 255) / 256);
   if (th) {
     hipLaunchKernelGGL((psi_init<R>), dim3(nb), dim3(256), 0, st, (const R*)temp, 0, p.t_ref,
+                       make_dk_shift<double>(p.ddk_dT, p.ddk_dT2, p.ddk_dT3, p.grating_period,
+                                             p.grating_a, p.grating_b, p.t_ref),
                        pl.dz, psi_work, n2);
   }
   // ---- forward sweep with checkpoints
@@ -236,7 +238,8 @@ static int adjoint_t(Plan& pl, const void* a_f_in, const void* a_sh_in, const do
     q.carry = carry;
     q.moments = moments;
     q.t_ref = (R)p.t_ref;
-    q.ddk = (R)p.ddk_dT;
+    q.dk = make_dk_shift<R>(p.ddk_dT, p.ddk_dT2, p.ddk_dT3, p.grating_period, p.grating_a,
+                            p.grating_b, p.t_ref);
     q.lens_f = (R)pl.lens_f;
     q.lens_sh = (R)pl.lens_sh;
     q.dz = (R)pl.dz;

@@ -298,7 +298,8 @@ struct RowAdjTArgs {
   const R* psi;           // Psi at the start of step s_second (or s_first when s_second < 0)
   Carry<R>* carry;        // [ny][nx]
   double* moments;        // [ny][nx][2] running sum of dL/dT (T - T_ref) and dL/dT
-  R t_ref, ddk, lens_f, lens_sh, dz;
+  R t_ref, lens_f, lens_sh, dz;
+  DkT<R> dk;              // mismatch shift of each cell's temperature
 };
 
 // Pull-back of one cell through the first half-step of s_first and the second
@@ -366,22 +367,24 @@ __device__ __forceinline__ void adj_cell(const RowAdjArgs<R>& p, const RowAdjTAr
     HalfStepT<R> c2{};
     if (p.s_second >= 0) {
       const R dT = pre.dT2;
-      c2 = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, q.ddk, psi, dT, h, qdz,
+      const R dkc = thermal_dk(dT, q.dk);
+      c2 = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, psi, dkc, dT, h, qdz,
                          q.lens_f, q.lens_sh);
       rk4_cell_t(ya, yb, c2, p.tf, p.ts, h, und);
-      psi += dT * q.dz;
+      psi += dkc * q.dz;
     }
     if (p.s_first >= 0) {
       const R dT = pre.dT1;
-      const HalfStepT<R> c1 = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, q.ddk, psi, dT,
-                                            (R)0, qdz, q.lens_f, q.lens_sh);
+      const HalfStepT<R> c1 = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, psi,
+                                            thermal_dk(dT, q.dk), dT, (R)0, qdz,
+                                            q.lens_f, q.lens_sh);
       R g = 0, gt = 0, gl = 0;
       rk4_vjp_t(ya, yb, la, lb, c1, p.tf, p.ts, q.lens_f, q.lens_sh, h, und, (R)0, g, gt, gl);
       acc[0] += (double)g;
       acc[1] += (double)gt;
       // step s_first is complete: its second half-step was pulled back earlier
       const R g_dk = gt + cr.z + q.dz * cr.x;              // dL/d dk_s for this cell
-      const R g_t = q.ddk * g_dk + gl + cr.w;              // dL/dT_s
+      const R g_t = thermal_dk_slope(dT, q.dk) * g_dk + gl + cr.w;   // dL/dT_s
       cr.x += g + cr.y;
       double* mo = q.moments + 2 * idx;
       mo[0] += (double)g_t * (double)dT;

@@ -75,10 +75,11 @@ __device__ __forceinline__ void rk4_cell(cx<R>& a, cx<R>& b, const HalfStep<R>& 
 
 // ---------------------------------------------------------------- temperature
 // With a temperature field the mismatch and the index are per cell.  On step s
-// the phase is phi = Phi_s + dk_s tau + ddk_dT (Psi_s + dT_s tau), tau = z - z_s,
-// where Phi_s + dk_s tau comes from the uniform table, dT_s = T_s - T_ref is the
-// mid-plane sample and Psi_s = sum_{s' < s} dT_s' dz is carried per cell.  The
-// thermal lens adds -i g_j dT_s A_j, g_j = (2 pi / lambda_j) dn/dT.
+// the phase is phi = Phi_s + dk_s tau + Psi_s + d_s tau, tau = z - z_s, where
+// Phi_s + dk_s tau comes from the uniform table, dT_s = T_s - T_ref is the
+// mid-plane sample, d_s = c1 dT_s + c2 dT_s^2 + c3 dT_s^3 is the cell's
+// thermal mismatch shift and Psi_s = sum_{s' < s} d_s' dz is carried per cell.
+// The thermal lens adds -i g_j dT_s A_j, g_j = (2 pi / lambda_j) dn/dT.
 template <typename R>
 struct HalfStepT {
   cx<R> cf[3], cs[3];
@@ -88,17 +89,62 @@ struct HalfStepT {
 __device__ __forceinline__ void sincos_r(float x, float* s, float* c) { sincosf(x, s, c); }
 __device__ __forceinline__ void sincos_r(double x, double* s, double* c) { sincos(x, s, c); }
 
-// Stage coefficients at tau0, tau0 + qdz, tau0 + 2 qdz for one cell (qdz =
-// dz/4 and stride 1 for a half-step; dz/2 and stride 2 for a full step).
+// Thermal mismatch shift d(dT) = dk(T) - dk(T_ref) of Eq. 4, dT = T - T_ref:
+// the dispersion part is the cubic dT (c1 + dT (c2 + dT c3)); the grating part
+// 2 pi/Lambda(T_ref) - 2 pi/Lambda(T), Lambda = Lambda25 u, u = 1 + a x + b x^2,
+// x = T - 25 C, is evaluated as g dT (a + b (2 xr + dT)) / u(T) with
+// g = 2 pi / (Lambda25 u(T_ref)) and xr = T_ref - 25 C, which has no
+// cancellation (g = 0 without a grating term).
+template <typename R>
+struct DkT {
+  R c1, c2, c3;           // dispersion cubic
+  R g, g25, a, b, xr;     // grating: 2 pi/(Lambda25 u_ref), 2 pi/Lambda25, a, b, T_ref - 25 C
+};
+
+// Built in FP64 on the host from the plan parameters (lam25 = 0: no grating term).
+template <typename R>
+inline DkT<R> make_dk_shift(double c1, double c2, double c3, double lam25, double a, double b,
+                            double t_ref) {
+  const double xr = t_ref - 298.15;
+  const double g25 = lam25 > 0.0 ? 2.0 * M_PI / lam25 : 0.0;
+  const double uref = 1.0 + xr * (a + xr * b);
+  DkT<R> k;
+  k.c1 = (R)c1;
+  k.c2 = (R)c2;
+  k.c3 = (R)c3;
+  k.g = (R)(g25 / uref);
+  k.g25 = (R)g25;
+  k.a = (R)(lam25 > 0.0 ? a : 0.0);
+  k.b = (R)(lam25 > 0.0 ? b : 0.0);
+  k.xr = (R)xr;
+  return k;
+}
+
+template <typename R>
+__device__ __forceinline__ R thermal_dk(R dT, const DkT<R>& k) {
+  const R x = k.xr + dT;
+  const R u = (R)1 + x * (k.a + x * k.b);
+  return dT * (k.c1 + dT * (k.c2 + dT * k.c3)) + k.g * dT * (k.a + k.b * (k.xr + x)) / u;
+}
+template <typename R>
+__device__ __forceinline__ R thermal_dk_slope(R dT, const DkT<R>& k) {
+  const R x = k.xr + dT;
+  const R u = (R)1 + x * (k.a + x * k.b);
+  return k.c1 + dT * ((R)2 * k.c2 + (R)3 * k.c3 * dT) + k.g25 * (k.a + (R)2 * k.b * x) / (u * u);
+}
+
+// Stage coefficients at tau0, tau0 + qdz, tau0 + 2 qdz for one cell with
+// carried phase psi, mismatch shift dkc and lens sample dT (qdz = dz/4 and
+// stride 1 for a half-step; dz/2 and stride 2 for a full step).
 template <typename R>
 __device__ __forceinline__ HalfStepT<R> thermal_coefs(const cx<R>* __restrict__ e, R kf, R ks,
-                                                      R ddk, R psi, R dT, R tau0, R qdz,
+                                                      R psi, R dkc, R dT, R tau0, R qdz,
                                                       R lens_f, R lens_sh, int stride = 1) {
   HalfStepT<R> h;
   R sn, c;
-  sincos_r(ddk * (psi + dT * tau0), &sn, &c);
+  sincos_r(psi + dkc * tau0, &sn, &c);
   cx<R> rho = {c, -sn};
-  sincos_r(ddk * dT * qdz, &sn, &c);
+  sincos_r(dkc * qdz, &sn, &c);
   const cx<R> step = {c, -sn};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -164,7 +210,8 @@ struct RowArgs {
   const R* temp;          // [nz][ny][nx] mid-plane samples
   R* psi;                 // [ny][nx] in: Psi at the oldest step touched; out: at the newest
   R* tap_psi;             // optional: Psi_{s_second} (adjoint recompute)
-  R t_ref, ddk, lens_f, lens_sh, dz;
+  R t_ref, lens_f, lens_sh, dz;
+  DkT<R> dk;              // mismatch shift of each cell's temperature
   // optional heat source (Sec. 2.2) of the state at this pass's step boundary
   // (after the second half-step of s_second, before the first of s_first)
   R* heat;                // [ny][nx] plane, or null
@@ -262,19 +309,21 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
       if (p.tap_psi) p.tap_psi[idx] = psi;
       if (p.s_second >= 0) {
         const R dT = p.temp[(size_t)p.s_second * n2 + idx] - p.t_ref;
-        const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, p.ddk, psi,
+        const R dkc = thermal_dk(dT, p.dk);
+        const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, psi, dkc,
                                              dT, p.h, qdz, p.lens_f, p.lens_sh);
         rk4_cell_t(va[m], vb[m], c, p.tf, p.ts, p.h, und);
-        psi += dT * p.dz;
+        psi += dkc * p.dz;
       }
       if (p.heat) p.heat[idx] = heat_density(va[m], vb[m], p);
       if (p.s_first >= 0) {
         const R dT = p.temp[(size_t)p.s_first * n2 + idx] - p.t_ref;
+        const R dkc = thermal_dk(dT, p.dk);
         const int st = p.full ? 2 : 1;
-        const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, p.ddk, psi, dT,
+        const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, psi, dkc, dT,
                                              (R)0, qdz * st, p.lens_f, p.lens_sh, st);
         rk4_cell_t(va[m], vb[m], c, p.tf, p.ts, p.h * st, und);
-        if (p.full) psi += dT * p.dz;
+        if (p.full) psi += dkc * p.dz;
       }
       // psi now holds Psi at the start of the newest step touched (s_first, or
       // s_second + 1 after a last pass, or s_first + 1 after a full step), so a
@@ -324,15 +373,19 @@ __global__ void __launch_bounds__(G * ROWS) row_pass(RowArgs<R> p) {
   row_body<R, N, G, ROWS, TH>(p, blockIdx.x);
 }
 
-// Psi at the start of step s_begin: sum_{s < s_begin} (T_s - T_ref) dz per cell
-// (FP64 accumulation); zero for s_begin = 0.
+// Psi at the start of step s_begin: sum_{s < s_begin} d(T_s - T_ref) dz per
+// cell, d the mismatch shift (FP64 accumulation); zero for s_begin = 0.
 template <typename R>
 __global__ void __launch_bounds__(256) psi_init(const R* __restrict__ temp, int s_begin, double t_ref,
-                                                double dz, R* __restrict__ psi, size_t n2) {
+                                                DkT<double> dk, double dz, R* __restrict__ psi,
+                                                size_t n2) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n2) return;
   double acc = 0.0;
-  for (int s = 0; s < s_begin; ++s) acc += ((double)temp[(size_t)s * n2 + i] - t_ref) * dz;
+  for (int s = 0; s < s_begin; ++s) {
+    const double dT = (double)temp[(size_t)s * n2 + i] - t_ref;
+    acc += thermal_dk(dT, dk) * dz;
+  }
   psi[i] = (R)acc;
 }
 
@@ -389,16 +442,18 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
     psi1 = psi0;
     if (p.s_second >= 0) {
       const R dT = p.temp[(size_t)p.s_second * n2 + idx] - p.t_ref;
-      c2t = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, p.ddk, psi0, dT, p.h, qdz,
+      const R dkc = thermal_dk(dT, p.dk);
+      c2t = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, psi0, dkc, dT, p.h, qdz,
                           p.lens_f, p.lens_sh);
-      psi1 += dT * p.dz;
+      psi1 += dkc * p.dz;
     }
     psi2 = psi1;
     if (p.s_first >= 0) {
       const R dT = p.temp[(size_t)p.s_first * n2 + idx] - p.t_ref;
-      c1t = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, p.ddk, psi1, dT, (R)0, qdz * stf,
+      const R dkc = thermal_dk(dT, p.dk);
+      c1t = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, psi1, dkc, dT, (R)0, qdz * stf,
                           p.lens_f, p.lens_sh, stf);
-      if (p.full) psi2 += dT * p.dz;
+      if (p.full) psi2 += dkc * p.dz;
     }
   } else {
     if (p.s_second >= 0) c2 = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);

@@ -355,9 +355,17 @@ int validate_params(const shg_params* p) {
   if (!finite_nonneg(p->alpha_f) || !finite_nonneg(p->alpha_sh) || !finite_nonneg(p->beta_f) ||
       !finite_nonneg(p->beta_sh))
     return fail(SHG_EINVAL, "absorption coefficients must be finite and >= 0");
-  if (!std::isfinite(p->dk0) || !std::isfinite(p->ddk_dT) || !std::isfinite(p->dn_dT) ||
-      !std::isfinite(p->t_ref))
-    return fail(SHG_EINVAL, "dk0, ddk_dT, dn_dT, t_ref must be finite");
+  if (!std::isfinite(p->dk0) || !std::isfinite(p->ddk_dT) || !std::isfinite(p->ddk_dT2) ||
+      !std::isfinite(p->ddk_dT3) || !std::isfinite(p->dn_dT) || !std::isfinite(p->t_ref))
+    return fail(SHG_EINVAL, "dk0, ddk_dT, ddk_dT2, ddk_dT3, dn_dT, t_ref must be finite");
+  if (!finite_nonneg(p->grating_period) || !std::isfinite(p->grating_a) ||
+      !std::isfinite(p->grating_b))
+    return fail(SHG_EINVAL, "grating_period must be finite and >= 0, grating_a/b finite");
+  if (p->grating_period > 0.0) {
+    const double x = p->t_ref - 298.15;
+    if (!(1.0 + x * (p->grating_a + x * p->grating_b) > 0.0))
+      return fail(SHG_EINVAL, "grating period must be positive at t_ref");
+  }
   if (p->checkpoint_every < 0) return fail(SHG_EINVAL, "checkpoint_every must be >= 0");
   if (!(std::fabs(p->walkoff_f) < M_PI / 2) || !(std::fabs(p->walkoff_sh) < M_PI / 2))
     return fail(SHG_EINVAL, "walk-off angles must be finite with |rho| < pi/2");
@@ -516,13 +524,17 @@ static int enqueue_forward_t(Plan& pl, const FwdIO& io, const double* dk_z, int 
     ra.temp = (const R*)io.temp;
     ra.psi = io.psi ? (R*)io.psi : psi;
     ra.t_ref = (R)p.t_ref;
-    ra.ddk = (R)p.ddk_dT;
+    ra.dk = make_dk_shift<R>(p.ddk_dT, p.ddk_dT2, p.ddk_dT3, p.grating_period, p.grating_a,
+                             p.grating_b, p.t_ref);
     ra.lens_f = (R)pl.lens_f;
     ra.lens_sh = (R)pl.lens_sh;
     ra.dz = (R)pl.dz;
     if (!io.psi) {
       hipLaunchKernelGGL((psi_init<R>), dim3((n2 + 255) / 256), dim3(256), 0, st, ra.temp, s0,
-                         p.t_ref, pl.dz, ra.psi, n2);
+                         p.t_ref,
+                         make_dk_shift<double>(p.ddk_dT, p.ddk_dT2, p.ddk_dT3, p.grating_period,
+                                               p.grating_a, p.grating_b, p.t_ref),
+                         pl.dz, ra.psi, n2);
     }
   }
   R* tap_psi = (R*)io.tap_psi;

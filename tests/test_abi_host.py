@@ -81,7 +81,8 @@ def create(lib, p, dtype=0, flags=0):
     (dict(n_sh=0.0), "n_sh"), (dict(alpha_f=-1.0), "absorption"),
     (dict(beta_sh=float("inf")), "absorption"), (dict(dk0=float("nan")), "dk0"),
     (dict(d_eff=float("inf")), "d_eff"), (dict(walkoff_sh=1.6), "walk-off"),
-    (dict(walkoff_f=float("nan")), "walk-off"),
+    (dict(walkoff_f=float("nan")), "walk-off"), (dict(ddk_dT3=float("nan")), "ddk_dT3"),
+    (dict(grating_period=-8e-6), "grating"), (dict(grating_period=8e-6, grating_a=-1.0, t_ref=300.0), "grating"),
 ])
 def test_invalid_params_rejected_before_device(lib, bad, needle):
     rc, h, msg = create(lib, good_params(**bad))

@@ -177,10 +177,21 @@ def thermal_small(n=32, nz=18, undepleted=False):
     return wl, temp
 
 
-@pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-4)])
-def test_thermal_adjoint_matches_oracle(dtype, tol):
+# cubic dispersion part and the printed MgO:sPPLT grating expansion (Eq. 4)
+CUBIC_DK = dict(ddk_dT=60.0, ddk_dT2=-15.0, ddk_dT3=4.0, grating_period=workloads.GRATING_PERIOD,
+                grating_a=workloads.GRATING_A, grating_b=workloads.GRATING_B)
+
+
+@pytest.mark.parametrize("dtype,tol,cubic", [("c128", 1e-10, False), ("c64", 1e-4, False),
+                                             ("c128", 1e-10, True), ("c64", 1e-4, True)])
+def test_thermal_adjoint_matches_oracle(dtype, tol, cubic):
+    """Per-cell mismatch and lens; with cubic, dk(T) carries quadratic and
+    cubic terms, so the temperature moments go through the slope c1 + 2 c2 dT
+    + 3 c3 dT^2 of each cell."""
     from paper_2410_04994_amd import Plan
     wl, temp = thermal_small()
+    if cubic:
+        wl = wl.with_(**CUBIC_DK)
     npdt = np.complex64 if dtype == "c64" else np.complex128
     rdt = np.float32 if dtype == "c64" else np.float64
     temp = temp.astype(rdt)

@@ -208,6 +208,34 @@ def test_temperature_field_forward(dtype):
     assert rel(ref["a_sh"], cold["a_sh"]) > 1e-2
 
 
+@pytest.mark.parametrize("dtype,grating", [("c64", False), ("c128", False), ("c64", True),
+                                           ("c128", True)])
+def test_temperature_field_cubic_mismatch(dtype, grating):
+    """dk(T) of Eq. 4: the cubic dispersion part (stand-in for the Sellmeier
+    indices) and, with grating, the printed Lambda(T) of MgO:sPPLT, split at a
+    resume point so that the carried thermal phase is rebuilt from the samples."""
+    wl, temp = thermal_case(n=64, nz=40)
+    wl = wl.with_(ddk_dT=60.0, ddk_dT2=-15.0, ddk_dT3=4.0)
+    if grating:
+        wl = wl.with_(grating_period=workloads.GRATING_PERIOD, grating_a=workloads.GRATING_A,
+                      grating_b=workloads.GRATING_B)
+    plan = make_plan(wl, dtype)
+    a0, b0 = inputs(wl, dtype)
+    gpu = run_gpu(plan, a0, b0, temp=temp)
+    ref = run_oracle(wl, a0, b0, temp=temp.astype(np.float64))
+    compare(wl, gpu, ref, dtype, "cubic dk(T) " + plan.describe())
+    part = run_gpu(plan, a0, b0, temp=temp, s_end=17)
+    rest = run_gpu(plan, part[0], part[1], temp=temp, s_begin=17)
+    compare(wl, rest, ref, dtype, "cubic dk(T) resume")
+    # the higher terms matter
+    lin = run_oracle(wl.with_(ddk_dT2=0.0, ddk_dT3=0.0, grating_period=0.0), a0, b0,
+                     temp=temp.astype(np.float64))
+    assert rel(ref["a_sh"], lin["a_sh"]) > 1e-2
+    if grating:
+        nog = run_oracle(wl.with_(grating_period=0.0), a0, b0, temp=temp.astype(np.float64))
+        assert rel(ref["a_sh"], nog["a_sh"]) > 1e-3
+
+
 def test_temperature_field_resume_and_profile():
     wl, temp = thermal_case(n=32, nz=24)
     rng = np.random.Generator(np.random.PCG64(3))
