@@ -457,15 +457,15 @@ __global__ void __launch_bounds__(G * ROWS) row_adj_pass(RowAdjArgs<R> p, RowAdj
   TwRegs<R, N, G> twr;
   tw_load(twr, t, p.tw);
   if (p.inv_in) {
-    fft_pre<R, N, G, true, 1>(va, a0, a1, t, twr);
-    fft_pre<R, N, G, true, 1>(vb, b0, b1, t, twr);
+    fft_pre<R, N, G, true, 1, (G <= 64)>(va, a0, a1, t, twr);
+    fft_pre<R, N, G, true, 1, (G <= 64)>(vb, b0, b1, t, twr);
   }
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int m = 0; m < E; ++m) adj_cell<R, TH>(p, q, row + t + G * m, n2, va[m], vb[m], acc);
   if (p.fwd_out) {
-    fft_pre<R, N, G, false, 1>(va, a0, a1, t, twr);
-    fft_pre<R, N, G, false, 1>(vb, b0, b1, t, twr);
+    fft_pre<R, N, G, false, 1, (G <= 64)>(va, a0, a1, t, twr);
+    fft_pre<R, N, G, false, 1, (G <= 64)>(vb, b0, b1, t, twr);
   }
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -507,7 +507,7 @@ __global__ void __launch_bounds__(WideShape<N>::threads) row_adj_pass_wide(RowAd
 #pragma unroll
       for (int m = 0; m < EF; ++m) v[m] = src[frow + t + G * m];
     }
-    fft_pre<R, N, G, true, 1>(v, q0, q1, t, twr, fth);
+    fft_pre<R, N, G, true, 1, (G <= 64)>(v, q0, q1, t, twr, fth);
     if (fth) {
 #pragma unroll
       for (int m = 0; m < EF; ++m) cell[ff][fr][pad16(t + G * m)] = v[m];
@@ -522,7 +522,7 @@ __global__ void __launch_bounds__(WideShape<N>::threads) row_adj_pass_wide(RowAd
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   adj_cell<R, TH>(p, q, pre, idx, la, lb, acc);
   if (p.fwd_out) {
-    __syncthreads();
+    // each thread rewrites only the cell it read (no barrier before the write)
     cell[0][cr][pad16(cxi)] = la;
     cell[1][cr][pad16(cxi)] = lb;
     __syncthreads();
@@ -530,7 +530,7 @@ __global__ void __launch_bounds__(WideShape<N>::threads) row_adj_pass_wide(RowAd
 #pragma unroll
       for (int m = 0; m < EF; ++m) v[m] = cell[ff][fr][pad16(t + G * m)];
     }
-    fft_pre<R, N, G, false, 1>(v, q0, q1, t, twr, fth);
+    fft_pre<R, N, G, false, 1, (G <= 64)>(v, q0, q1, t, twr, fth);
     if (fth) {
       cx<R>* dst = ff ? p.lb : p.la;
 #pragma unroll

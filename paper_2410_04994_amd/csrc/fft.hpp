@@ -335,8 +335,26 @@ __device__ __forceinline__ void tw_load(TwRegs<R, N, G>& T, int t, const Tw<R>* 
   tw_gather<R, N, G, 1, N>(T.w, t, tw);
 }
 
+// Barrier between Stockham passes.  WAVE: every transform belongs to the
+// threads of one wavefront, whose LDS buffers no other wavefront touches; a
+// wavefront's LDS operations complete in issue order, so a wavefront-level
+// barrier that keeps the compiler from moving LDS accesses across it is
+// enough (no s_barrier, no wait for the writes to land).  Otherwise a block
+// barrier.
+template <bool WAVE>
+__device__ __forceinline__ void pass_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // Stockham pass reading its twiddles from the prefetched registers.
-template <typename R, int N, int G, bool INV, int NS, int REM, bool FIRST, int STRIDE>
+template <typename R, int N, int G, bool INV, int NS, int REM, bool FIRST, int STRIDE,
+          bool WAVE = false>
 __device__ __forceinline__ void stockham_pre(cx<R> (&v)[N / G], LdsView<R, STRIDE> in,
                                              LdsView<R, STRIDE> out, int t, const Tw<R>* twr,
                                              bool active) {
@@ -368,19 +386,32 @@ __device__ __forceinline__ void stockham_pre(cx<R> (&v)[N / G], LdsView<R, STRID
     }
   }
   if constexpr (!LAST) {
-    __syncthreads();
+    if constexpr (WAVE) {
+      if (!active) return;
+    }
+    pass_sync<WAVE>();
     constexpr int used = NS > 1 ? NB * (RP - 1) : 0;
-    stockham_pre<R, N, G, INV, NS * RP, REM / RP, false, STRIDE>(v, out, in, t, twr + used,
-                                                                active);
+    stockham_pre<R, N, G, INV, NS * RP, REM / RP, false, STRIDE, WAVE>(v, out, in, t, twr + used,
+                                                                      active);
   }
 }
 
-template <typename R, int N, int G, bool INV, int STRIDE>
+// Whole transform of the registers v with prefetched twiddles; one leading
+// barrier protects LDS reuse.  Without WAVE all threads of the block must call
+// it (threads with active = false only take part in the barriers).  WAVE (see
+// pass_sync) needs each transform's threads, and the buffers b0, b1, to
+// belong to one wavefront; inactive wavefronts then skip it.
+template <typename R, int N, int G, bool INV, int STRIDE, bool WAVE = false>
 __device__ __forceinline__ void fft_pre(cx<R> (&v)[N / G], LdsView<R, STRIDE> b0,
                                         LdsView<R, STRIDE> b1, int t, const TwRegs<R, N, G>& T,
                                         bool active = true) {
-  if constexpr (pick_radix<N / G, N>::value < N) __syncthreads();
-  stockham_pre<R, N, G, INV, 1, N, true, STRIDE>(v, b0, b1, t, T.w, active);
+  static_assert(!WAVE || G * STRIDE <= 64,
+                "a wavefront-synchronised transform must fit one wavefront");
+  if constexpr (WAVE) {
+    if (!active) return;
+  }
+  if constexpr (pick_radix<N / G, N>::value < N) pass_sync<WAVE>();
+  stockham_pre<R, N, G, INV, 1, N, true, STRIDE, WAVE>(v, b0, b1, t, T.w, active);
 }
 
 // Whole transform of the registers v.  All threads of the block must call it

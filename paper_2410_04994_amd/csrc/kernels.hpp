@@ -288,8 +288,8 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
     if (p.s_first >= 0) c1 = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, stf);
   }
   if (p.inv_in) {
-    fft_pre<R, N, G, true, 1>(va, a0, a1, t, twr);
-    fft_pre<R, N, G, true, 1>(vb, b0, b1, t, twr);
+    fft_pre<R, N, G, true, 1, (G <= 64)>(va, a0, a1, t, twr);
+    fft_pre<R, N, G, true, 1, (G <= 64)>(vb, b0, b1, t, twr);
   }
   const bool und = p.undepleted != 0;
   if (p.tap_a) {
@@ -345,8 +345,8 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
     }
   }
   if (p.fwd_out) {
-    fft_pre<R, N, G, false, 1>(va, a0, a1, t, twr);
-    fft_pre<R, N, G, false, 1>(vb, b0, b1, t, twr);
+    fft_pre<R, N, G, false, 1, (G <= 64)>(va, a0, a1, t, twr);
+    fft_pre<R, N, G, false, 1, (G <= 64)>(vb, b0, b1, t, twr);
   }
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -465,7 +465,7 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
 #pragma unroll
       for (int m = 0; m < EF; ++m) v[m] = src[frow + t + G * m];
     }
-    fft_pre<R, N, G, true, 1>(v, q0, q1, t, twr, fth);
+    fft_pre<R, N, G, true, 1, (G <= 64)>(v, q0, q1, t, twr, fth);
     if (fth) {
 #pragma unroll
       for (int m = 0; m < EF; ++m) cell[ff][fr][pad16(t + G * m)] = v[m];
@@ -494,7 +494,8 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
     if (p.s_first >= 0) rk4_cell(a, b, c1, p.tf, p.ts, p.h * stf, und);
   }
   if (p.fwd_out) {
-    __syncthreads();   // every thread has read its cell before it is overwritten
+    // each thread rewrites only the cell it read, so no barrier is needed
+    // before the write; the transform wavefronts read after the barrier
     cell[0][cr][pad16(cxi)] = a;
     cell[1][cr][pad16(cxi)] = b;
     __syncthreads();
@@ -502,7 +503,7 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
 #pragma unroll
       for (int m = 0; m < EF; ++m) v[m] = cell[ff][fr][pad16(t + G * m)];
     }
-    fft_pre<R, N, G, false, 1>(v, q0, q1, t, twr, fth);
+    fft_pre<R, N, G, false, 1, (G <= 64)>(v, q0, q1, t, twr, fth);
     if (fth) {
       cx<R>* dst = ff ? p.bout : p.aout;
 #pragma unroll
@@ -547,8 +548,12 @@ __device__ __forceinline__ int xcd_linear_block(int b, int nblk) {
   return (nblk % 8 == 0) ? (b % 8) * (nblk / 8) + b / 8 : b;
 }
 
+// Thread t * TC + c works on element rows t + G m of column c, so that the TC
+// columns of a row are read by adjacent lanes.  A block of at most 64 threads
+// is one wavefront, and its transforms then synchronise at wavefront level.
 template <typename R, int N, int G, int TC>
 __device__ __forceinline__ void col_body(const ColArgs<R>& p) {
+  constexpr bool WAVE = G * TC <= 64;
   constexpr int E = N / G;
   constexpr int P = padded_len<N>();
   __shared__ cx<R> lds[2][P * TC];
@@ -579,13 +584,13 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& p) {
   const LdsView<R, TC> b0{&lds[0][c]}, b1{&lds[1][c]};
   TwRegs<R, N, G> twr;
   tw_load(twr, t, p.tw);
-  fft_pre<R, N, G, false, TC>(v, b0, b1, t, twr);
+  fft_pre<R, N, G, false, TC, WAVE>(v, b0, b1, t, twr);
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const double vr = (double)v[m].re, vi = (double)v[m].im;
     v[m] = {(R)(vr * mr[m] - vi * mi[m]), (R)(vr * mi[m] + vi * mr[m])};
   }
-  fft_pre<R, N, G, true, TC>(v, b0, b1, t, twr);
+  fft_pre<R, N, G, true, TC, WAVE>(v, b0, b1, t, twr);
 #pragma unroll
   for (int m = 0; m < E; ++m) col[(size_t)(t + G * m) * p.nx] = v[m];
 }
