@@ -65,10 +65,25 @@ def fwd_adj(device, reps=2):
 
     run()
     sec = _timed(run, reps, torch)
-    return {"workload": wl.name, "schedule": plan.describe(), "workspace_MB": round(ws.numel() / 2**20, 1),
-            "cell_steps": wl.cell_steps, "ms_per_fwd_adj": round(sec * 1e3, 3),
-            "cell_steps_per_s": round(wl.cell_steps / sec, 1),
-            "frac_hbm_at_224B": round(wl.cell_steps / sec * 224 / 8e12, 4)}
+    out = {"workload": wl.name, "schedule": plan.describe(), "workspace_MB": round(ws.numel() / 2**20, 1),
+           "cell_steps": wl.cell_steps, "ms_per_fwd_adj": round(sec * 1e3, 3),
+           "cell_steps_per_s": round(wl.cell_steps / sec, 1),
+           "frac_hbm_at_224B": round(wl.cell_steps / sec * 224 / 8e12, 4)}
+    # checkpoints every 32 steps, each segment recomputed in the reverse sweep
+    plan32 = Plan(wl.params(), "c64", checkpoint_every=32)
+    autotune.tune_single(plan32)
+    ws32 = plan32.workspace(adjoint=True, device=device)
+
+    def run32():
+        plan32.adjoint(a0, b0, power_weights=w, dk_z=dk, want_dk=True, workspace=ws32)
+
+    run32()
+    sec32 = _timed(run32, reps, torch)
+    out["k32"] = {"schedule": plan32.describe(), "workspace_MB": round(ws32.numel() / 2**20, 1),
+                  "ms_per_fwd_adj": round(sec32 * 1e3, 3),
+                  "cell_steps_per_s": round(wl.cell_steps / sec32, 1),
+                  "frac_hbm_at_224B": round(wl.cell_steps / sec32 * 224 / 8e12, 4)}
+    return out
 
 
 FP64_MFMA_PEAK = 78.6e12
