@@ -291,10 +291,16 @@ def test_lnl_split_order(dtype):
     assert rel(lnl["a_sh"], nln["a_sh"]) > 1e-6
 
 
-@pytest.mark.parametrize("dtype", ["c64", "c128"])
-def test_lnl_with_temperature_field_and_resume(dtype):
+@pytest.mark.parametrize("dtype,dk_t", [("c64", False), ("c128", False), ("c64", True)])
+def test_lnl_with_temperature_field_and_resume(dtype, dk_t):
+    """L/2 - N - L/2 with per-cell mismatch and lens; dk_t adds the cubic
+    dispersion part and the grating-period expansion of dk(T)."""
     wl, temp = thermal_case(n=32, nz=24)
     wl = wl.with_(split="LNL")
+    if dk_t:
+        wl = wl.with_(ddk_dT=60.0, ddk_dT2=-15.0, ddk_dT3=4.0,
+                      grating_period=workloads.GRATING_PERIOD, grating_a=workloads.GRATING_A,
+                      grating_b=workloads.GRATING_B)
     plan = make_plan(wl, dtype)
     a0, b0 = inputs(wl, dtype)
     full = run_gpu(plan, a0, b0, temp=temp)
