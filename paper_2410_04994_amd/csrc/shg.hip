@@ -236,8 +236,8 @@ struct SchedRow {
 };
 static const SchedRow kSingle[] = {{16, 1, 256, 4, 16}, {32, 1, 256, 4, 8}, {64, 1, 256, 4, 4},
                                    {128, 1, 256, 4, 2}, {256, 1, 256, 4, 2}, {512, 1, 512, 8, 4}};
-static const SchedRow kBatch[] = {{16, 4, 64, 4, 16}, {32, 4, 64, 4, 16}, {64, 4, 64, 4, 8},
-                                  {128, 4, 64, 8, 4}, {256, 4, 64, 8, 8}, {512, 4, 64, 8, 4}};
+static const SchedRow kBatch[] = {{16, 4, 64, 4, 16}, {32, 4, 64, 4, 8}, {64, 4, 64, 4, 4},
+                                  {128, 4, 64, 16, 8}, {256, 4, 64, 16, 8}, {512, 4, 64, 8, 4}};
 
 static bool apply_row(Plan& pl, int re, int rw, int* rows) { return row_supported(pl, re, rw, rows); }
 
