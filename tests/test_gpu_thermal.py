@@ -213,3 +213,33 @@ def test_self_consistent_loop_with_cg():
                           torch.zeros(a0.shape, dtype=torch.complex128, device="cuda"),
                           tol_t=1e-7, solve_tol=1e-13, max_iter=20000)
     assert np.max(np.abs(out["t_nodes"].cpu().numpy() - ref_t)) < 1e-7 * np.ptp(ref_t)
+
+
+def test_full_size_temperature_field_march_deposits_the_lost_power():
+    """The 50 W temperature-field workload at its full size (512 x 512 x 2000,
+    the synthetic T field), in the schedule the benchmark uses: the heat source
+    written at the 2001 step boundaries, integrated over the crystal
+    (trapezoid in z), equals the power the two fields lose.  The lens and the
+    mismatch only rotate phases, so this holds at any size; the residual is
+    the O(dz^2) of the trapezoid and the FP32 rounding of the powers."""
+    import workloads
+    from paper_2410_04994_amd import Plan, autotune, beams as gbeams
+    wl = workloads.c5_thermal_c64()
+    print(f"case: {wl.name}", flush=True)
+    temp = torch.from_numpy(workloads.radial_temperature_profile(wl).astype(np.float32)).cuda()
+    plan = Plan(wl.params(), "c64")
+    autotune.tune_single(plan)
+    a = gbeams.pump_for(wl, dtype=torch.complex64, device="cuda")
+    c = ssfm.coefficients(wl.params())
+    p_in = ssfm.power(a.cpu().numpy().astype(complex), wl.n_f, c.dx, c.dy)
+    b = torch.zeros_like(a)
+    heat, powers = plan.propagate_heat(a, b, temp=temp)
+    torch.cuda.synchronize()
+    del temp
+    per_plane = heat.double().sum(dim=(1, 2)).cpu().numpy() * c.dx * c.dy
+    absorbed = float(np.trapezoid(per_plane, dx=c.dz))
+    p_f, p_sh = powers.cpu().numpy()
+    lost = p_in - (p_f + p_sh)
+    assert p_sh > 0.1 * p_in                              # strong conversion
+    assert lost > 0.0
+    assert abs(absorbed / lost - 1) < 1e-3, (absorbed, lost)
