@@ -234,3 +234,46 @@ def test_thermal_scalar_gradients_by_finite_differences():
         fd_sc = (f(t0, sc + h) - f(t0, sc - h)) / (2 * h)
     assert abs(t0.grad.item() - fd_t0) <= 1e-5 * abs(fd_t0) + 1e-12
     assert abs(sc.grad.item() - fd_sc) <= 1e-5 * abs(fd_sc) + 1e-12
+
+
+def test_full_size_differentiation_config_against_central_differences():
+    """The differentiation workload at its full size and as stated (256 x 256 x
+    1000, 20 mm, 10 W, xi = 2.84, phase mask N(0, 0.1^2), checkpoints every 32
+    steps, recomputed): the complex64 adjoint's derivative of P_SH along 64
+    random directions of (theta, dk_z) against central differences (h = 1e-3)
+    of the complex128 march.  A dk direction moves the accumulated phase by
+    about h rad: delta dk_s = h v_s / (dz sqrt(nz))."""
+    from paper_2410_04994_amd import Plan, beams
+    wl = workloads.c4_diff_c64()
+    print(f"case: {wl.name} K=32", flush=True)
+    theta0 = torch.from_numpy(workloads.phase_noise(wl)).cuda()
+    dk0 = torch.full((wl.nz,), wl.dk0, dtype=torch.float64, device="cuda")
+    w = torch.tensor([0.0, 1.0], dtype=torch.float64, device="cuda")
+    plan = Plan(wl.params(), "c64", checkpoint_every=32)
+    a0 = beams.pump_for(wl, theta=theta0, dtype=torch.complex64)
+    res = plan.adjoint(a0, torch.zeros_like(a0), power_weights=w, dk_z=dk0, want_dk=True)
+    # dP/dtheta: a = |a| e^{i theta}, da/dtheta = i a, g = dP/dRe + i dP/dIm
+    g_theta = (torch.conj(res["g_f"]) * (1j * a0)).real.double()
+    g_dk = res["g_dk"]
+    ref = Plan(wl.params(), "c128")
+
+    def p_sh(theta, dk):
+        a = beams.pump_for(wl, theta=theta, dtype=torch.complex128)
+        pw = ref.propagate(a, torch.zeros_like(a), dk_z=dk)
+        return float(pw[1])
+
+    rng = np.random.Generator(np.random.PCG64(40))
+    dz = wl.lcr / wl.nz
+    h = 1e-3
+    fd, an = [], []
+    for _ in range(64):
+        v = torch.from_numpy(rng.normal(size=(wl.ny, wl.nx))).cuda()
+        vk = torch.from_numpy(rng.normal(size=wl.nz)).cuda() / (dz * math.sqrt(wl.nz))
+        fd.append((p_sh(theta0 + h * v, dk0 + h * vk) - p_sh(theta0 - h * v, dk0 - h * vk)) / (2 * h))
+        an.append(float((g_theta * v).sum() + (g_dk * vk).sum()))
+    fd, an = np.array(fd), np.array(an)
+    # relative L2 over the 64 directions (a single direction can have a
+    # derivative near zero, so per-direction ratios are not used)
+    err = float(np.linalg.norm(fd - an) / np.linalg.norm(fd))
+    print(f"relative L2 difference over 64 directions: {err:.2e}", flush=True)
+    assert err < 1e-4
