@@ -180,3 +180,29 @@ def test_batch_rejects_mixed_split_orders():
     b = [torch.zeros_like(x) for x in a]
     with pytest.raises(ShgError, match="split"):
         propagate_batch(plans, a, b)
+
+
+def test_full_size_sweep_against_single_marches_and_oracle():
+    """The 512-instance sweep at its full step counts (64/128/256 in 1:2:1, nz
+    in [200, 1000]) with the schedules the benchmark uses: 16 sampled
+    instances equal their own single-instance marches bit for bit, and the
+    shortest instance of each size matches the oracle."""
+    from paper_2410_04994_amd import Plan
+    wls = workloads.c3_batch()
+    print(f"case: c3 sweep, {len(wls)} instances, full nz", flush=True)
+    plans, ins, A, B, pw = run_batch(wls)
+    rng = np.random.Generator(np.random.PCG64(78))
+    for i in rng.choice(len(wls), size=16, replace=False):
+        w = wls[i]
+        p = Plan(w.params(), "c64")
+        p.set_schedule(*batch_schedule(plans[i]))
+        a = torch.from_numpy(ins[i][0]).cuda()
+        b = torch.from_numpy(ins[i][1]).cuda()
+        p.propagate(a, b)
+        torch.cuda.synchronize()
+        assert np.array_equal(a.cpu().numpy(), A[i]) and np.array_equal(b.cpu().numpy(), B[i]), i
+    for size in (64, 128, 256):
+        idx = min((i for i, w in enumerate(wls) if w.nx == size), key=lambda i: wls[i].nz)
+        w = wls[idx]
+        ref = run_oracle(w, ins[idx][0], ins[idx][1])
+        compare(w, (A[idx], B[idx], pw[idx]), ref, "c64", f"sweep[{idx}] {size}x{size}x{w.nz}")
