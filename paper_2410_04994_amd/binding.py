@@ -117,8 +117,10 @@ def _torch():
     return torch
 
 
-def _ptr(t, what: str, dtype=None):
-    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+def _ptr(t, what: str, dtype=None, numel: Optional[int] = None, nbytes: Optional[int] = None):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL).  The kernels
+    read and write numel elements (or nbytes bytes) through it, so a smaller
+    tensor is refused here."""
     if t is None:
         return None
     torch = _torch()
@@ -128,6 +130,10 @@ def _ptr(t, what: str, dtype=None):
         raise ValueError(f"{what} must be contiguous")
     if dtype is not None and t.dtype != dtype:
         raise ValueError(f"{what} must have dtype {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{what} holds {t.numel()} elements, needs {numel}")
+    if nbytes is not None and t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{what} holds {t.numel() * t.element_size()} bytes, needs {nbytes}")
     return t.data_ptr()
 
 
@@ -217,8 +223,25 @@ class Plan:
         _check(load_library().shg_plan_describe(self.handle, buf, 256))
         return buf.value.decode()
 
+    @property
+    def cells(self) -> int:
+        return int(self.params["nx"]) * int(self.params["ny"])
+
+    @property
+    def nz(self) -> int:
+        return int(self.params["nz"])
+
     def _field(self, t, what):
-        return _ptr(t, what, self.complex_dtype)
+        return _ptr(t, what, self.complex_dtype, numel=self.cells)
+
+    def _dk(self, t):
+        return _ptr(t, "dk_z", _torch().float64, numel=self.nz)
+
+    def _temp(self, t):
+        return _ptr(t, "temp", self.real_dtype, numel=self.nz * self.cells)
+
+    def _ws_ptr(self, t, adjoint: bool):
+        return _ptr(t, "workspace", nbytes=self.workspace_bytes(adjoint) if t is not None else None)
 
     # ------------------------------------------------------------------ calls
     def propagate(self, a_f, a_sh, dk_z=None, temp=None, s_begin: int = 0, s_end: Optional[int] = None,
@@ -231,9 +254,9 @@ class Plan:
             powers = torch.empty(2, dtype=torch.float64, device=a_f.device)
         _check(load_library().shg_propagate(
             self.handle, self._field(a_f, "a_f"), self._field(a_sh, "a_sh"),
-            _ptr(dk_z, "dk_z", torch.float64), _ptr(temp, "temp", self.real_dtype),
-            int(s_begin), int(s_end), _ptr(workspace, "workspace"),
-            _ptr(powers, "powers", torch.float64), _stream(stream)))
+            self._dk(dk_z), self._temp(temp), int(s_begin), int(s_end),
+            self._ws_ptr(workspace, False), _ptr(powers, "powers", torch.float64, numel=2),
+            _stream(stream)))
         return powers
 
     def propagate_heat(self, a_f, a_sh, dk_z=None, temp=None, heat=None, workspace=None,
@@ -249,9 +272,10 @@ class Plan:
             powers = torch.empty(2, dtype=torch.float64, device=a_f.device)
         _check(load_library().shg_propagate_heat(
             self.handle, self._field(a_f, "a_f"), self._field(a_sh, "a_sh"),
-            _ptr(dk_z, "dk_z", torch.float64), _ptr(temp, "temp", self.real_dtype),
-            _ptr(heat, "heat", self.real_dtype), _ptr(workspace, "workspace"),
-            _ptr(powers, "powers", torch.float64), _stream(stream)))
+            self._dk(dk_z), self._temp(temp),
+            _ptr(heat, "heat", self.real_dtype, numel=(self.nz + 1) * self.cells),
+            self._ws_ptr(workspace, False), _ptr(powers, "powers", torch.float64, numel=2),
+            _stream(stream)))
         return heat, powers
 
     def adjoint(self, a_f_in, a_sh_in, g_f_out=None, g_sh_out=None, power_weights=None, dk_z=None,
@@ -271,13 +295,15 @@ class Plan:
             workspace = self.workspace(adjoint=True, device=dev)
         _check(load_library().shg_propagate_adjoint(
             self.handle, self._field(a_f_in, "a_f_in"), self._field(a_sh_in, "a_sh_in"),
-            _ptr(dk_z, "dk_z", torch.float64), _ptr(temp, "temp", self.real_dtype),
+            self._dk(dk_z), self._temp(temp),
             self._field(g_f_out, "g_f_out"), self._field(g_sh_out, "g_sh_out"),
-            _ptr(power_weights, "power_weights", torch.float64),
+            _ptr(power_weights, "power_weights", torch.float64, numel=2),
             self._field(g_f, "g_f_in"), self._field(g_sh, "g_sh_in"),
-            _ptr(g_dk, "g_dk_z", torch.float64), _ptr(g_t, "g_t_moments", torch.float64),
+            _ptr(g_dk, "g_dk_z", torch.float64, numel=self.nz),
+            _ptr(g_t, "g_t_moments", torch.float64, numel=2),
             self._field(a_f, "a_f_out"), self._field(a_sh, "a_sh_out"),
-            _ptr(powers, "powers", torch.float64), _ptr(workspace, "workspace"), _stream(stream)))
+            _ptr(powers, "powers", torch.float64, numel=2), self._ws_ptr(workspace, True),
+            _stream(stream)))
         out = {"g_f": g_f, "g_sh": g_sh, "a_f": a_f, "a_sh": a_sh, "powers": powers}
         if want_dk:
             out["g_dk"] = g_dk
@@ -314,9 +340,13 @@ def propagate_batch(plans: Sequence[Plan], a_f: Sequence, a_sh: Sequence, dk_z: 
     fs = (_VP * n)(*[p._field(t, "a_sh[i]") for p, t in zip(plans, a_sh)])
     dk = None
     if dk_z is not None:
-        dk = (_VP * n)(*[_ptr(d, "dk_z[i]", torch.float64) for d in dk_z])
-    _check(load_library().shg_propagate_batch(n, hp, fa, fs, dk, _ptr(workspace, "workspace"),
-                                              _ptr(powers, "powers", torch.float64), _stream(stream)))
+        dk = (_VP * n)(*[p._dk(d) for p, d in zip(plans, dk_z)])
+    ws = None
+    if workspace is not None:
+        ws = _ptr(workspace, "workspace", nbytes=batch_workspace_bytes(plans))
+    _check(load_library().shg_propagate_batch(n, hp, fa, fs, dk, ws,
+                                              _ptr(powers, "powers", torch.float64, numel=2 * n),
+                                              _stream(stream)))
     return powers
 
 
@@ -386,10 +416,14 @@ class Thermal:
             t_mid = torch.empty((n[0] - 1, n[1], n[2]), dtype=self.real_dtype, device=dev)
         it = _I32()
         res = _F64()
+        nodes = self.node_shape[0] * self.node_shape[1] * self.node_shape[2]
+        mids = nodes - self.node_shape[1] * self.node_shape[2]
         _check(load_library().shg_thermal_solve(
-            self.handle, _ptr(heat, "heat", self.real_dtype), _ptr(t_nodes, "t_nodes", self.real_dtype),
-            _ptr(t_mid, "t_mid", self.real_dtype), float(tol), int(max_iter),
-            _ptr(workspace if workspace is not None else self.workspace(dev), "workspace"),
+            self.handle, _ptr(heat, "heat", self.real_dtype, numel=nodes),
+            _ptr(t_nodes, "t_nodes", self.real_dtype, numel=nodes),
+            _ptr(t_mid, "t_mid", self.real_dtype, numel=mids), float(tol), int(max_iter),
+            _ptr(workspace if workspace is not None else self.workspace(dev), "workspace",
+                 nbytes=self.workspace_bytes()),
             ctypes.byref(it), ctypes.byref(res), _stream(stream)))
         return t_nodes, t_mid, int(it.value), float(res.value)
 
@@ -421,12 +455,15 @@ def self_consistent(plan: Plan, thermal: Thermal, a_f0, a_sh0, dk_z=None, t_node
     t_mid = torch.empty((n[0] - 1, n[1], n[2]), dtype=thermal.real_dtype, device=dev)
     outer = _I32()
     change = _F64()
+    nodes = n[0] * n[1] * n[2]
     _check(load_library().shg_self_consistent(
         plan.handle, thermal.handle, plan._field(a_f0, "a_f0"), plan._field(a_sh0, "a_sh0"),
-        _ptr(dk_z, "dk_z", torch.float64), plan._field(a_f, "a_f"), plan._field(a_sh, "a_sh"),
-        _ptr(t_nodes, "t_nodes", thermal.real_dtype), _ptr(t_mid, "t_mid", thermal.real_dtype),
+        plan._dk(dk_z), plan._field(a_f, "a_f"), plan._field(a_sh, "a_sh"),
+        _ptr(t_nodes, "t_nodes", thermal.real_dtype, numel=nodes),
+        _ptr(t_mid, "t_mid", thermal.real_dtype, numel=nodes - n[1] * n[2]),
         float(tol_t), int(max_outer), float(solve_tol), int(max_iter),
-        _ptr(workspace if workspace is not None else thermal.workspace(dev), "workspace"),
+        _ptr(workspace if workspace is not None else thermal.workspace(dev), "workspace",
+             nbytes=thermal.workspace_bytes()),
         ctypes.byref(outer), ctypes.byref(change), _stream(stream)))
     return {"a_f": a_f, "a_sh": a_sh, "t_nodes": t_nodes, "t_mid": t_mid,
             "outer": int(outer.value), "change": float(change.value)}

@@ -161,6 +161,21 @@ def test_invalid_step_range_and_fields():
             plan.propagate(a, b, s_begin=s0, s_end=s1)
     with pytest.raises(ValueError):
         plan.propagate(a.to(torch.complex128), b)
+    # buffers smaller than the kernels address are refused before any launch
+    small = torch.zeros((64, 32), dtype=torch.complex64, device="cuda")
+    with pytest.raises(ValueError, match="a_sh holds"):
+        plan.propagate(a, small)
+    with pytest.raises(ValueError, match="dk_z holds"):
+        plan.propagate(a, b, dk_z=torch.zeros(9, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError, match="temp holds"):
+        plan.propagate(a, b, temp=torch.zeros((9, 64, 64), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError, match="workspace holds"):
+        plan.propagate(a, b, workspace=torch.zeros(plan.workspace_bytes() - 1, dtype=torch.uint8,
+                                                   device="cuda"))
+    with pytest.raises(ValueError, match="heat holds"):
+        plan.propagate_heat(a, b, heat=torch.zeros((10, 64, 64), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError, match="powers holds"):
+        plan.propagate(a, b, powers=torch.zeros(1, dtype=torch.float64, device="cuda"))
 
 
 def test_explicit_workspace_and_no_powers():
