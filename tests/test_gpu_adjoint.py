@@ -277,3 +277,31 @@ def test_full_size_differentiation_config_against_central_differences():
     err = float(np.linalg.norm(fd - an) / np.linalg.norm(fd))
     print(f"relative L2 difference over 64 directions: {err:.2e}", flush=True)
     assert err < 1e-4
+
+
+def test_full_size_thermal_scalar_gradients_against_central_differences():
+    """The temperature-field workload at its full size (512 x 512 x 2000, 50 W,
+    the synthetic T field): dP_SH/d(dT scale) and dP_SH/dT0 from the complex64
+    adjoint (temperature moments, automatic K) against central differences of
+    the complex128 march."""
+    from paper_2410_04994_amd import Plan, beams
+    from paper_2410_04994_amd.autograd import thermal_powers
+    wl = workloads.c5_thermal_c64()
+    print(f"case: {wl.name}", flush=True)
+    prof = torch.from_numpy(workloads.radial_temperature_profile(wl) - wl.extra["t0"]).cuda()
+    t0 = torch.tensor(wl.extra["t0"], dtype=torch.float64, device="cuda", requires_grad=True)
+    sc = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    plan = Plan(wl.params(), "c64")
+    a = beams.pump_for(wl, dtype=torch.complex64)
+    thermal_powers(plan, a, torch.zeros_like(a), t0, sc, prof)[1].backward()
+    ref = Plan(wl.params(), "c128")
+    a128 = beams.pump_for(wl, dtype=torch.complex128)
+    with torch.no_grad():
+        f = lambda tt, ss: thermal_powers(ref, a128, torch.zeros_like(a128), tt, ss, prof)[1].item()
+        h = 1e-3
+        fd_t0 = (f(t0 + h, sc) - f(t0 - h, sc)) / (2 * h)
+        fd_sc = (f(t0, sc + h) - f(t0, sc - h)) / (2 * h)
+    print(f"dP/dT0 {t0.grad.item():.6e} vs {fd_t0:.6e}; dP/dscale {sc.grad.item():.6e} vs {fd_sc:.6e}",
+          flush=True)
+    assert abs(t0.grad.item() - fd_t0) <= 1e-3 * abs(fd_t0)
+    assert abs(sc.grad.item() - fd_sc) <= 1e-3 * abs(fd_sc)
