@@ -95,7 +95,7 @@ typedef struct {
   double t_ref;           /* reference temperature [K]                         */
   uint32_t flags;         /* SHG_UNDEPLETED | SHG_NO_GRAPH                      */
   int32_t checkpoint_every; /* adjoint checkpoint interval K (0 -> automatic:  */
-                            /* K = nz when nz staged steps fit in 4 GiB)       */
+                            /* K = nz when nz staged steps fit in 16 GiB)      */
   double walkoff_f, walkoff_sh; /* spatial walk-off angles rho_F, rho_SH [rad], */
                             /* |rho| < pi/2; 0 for quasi-phase matching        */
   double ddk_dT2, ddk_dT3;  /* quadratic and cubic terms of dk(T) [rad/(m K^2)],*/

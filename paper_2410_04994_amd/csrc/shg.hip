@@ -383,7 +383,7 @@ static constexpr double kC = 299792458.0;
 // only the first nz - K steps are recomputed.  K = nz (nothing recomputed) when
 // that fits in kAdjointStateBudget, else the largest K whose checkpoints and
 // staging fit, but at least ceil(sqrt(nz)).
-static constexpr size_t kAdjointStateBudget = size_t(4) << 30;
+static constexpr size_t kAdjointStateBudget = size_t(16) << 30;
 
 static int auto_checkpoint(int nz, size_t cells, int real_bytes) {
   const size_t per_step = cells * 5 * (size_t)real_bytes;

@@ -86,6 +86,32 @@ def fwd_adj(device, reps=2):
     return out
 
 
+def thermal_fwd_adj(device, reps=2):
+    """Forward + adjoint of the 512 x 512 x 2000 temperature-field workload
+    with the temperature moments (the gradients in dT scale and T0), automatic
+    checkpoint interval."""
+    import torch
+    import workloads
+    from paper_2410_04994_amd import Plan, beams, autotune
+    wl = workloads.c5_thermal_c64()
+    plan = Plan(wl.params(), "c64")
+    autotune.tune_single(plan)
+    temp = torch.from_numpy(workloads.radial_temperature_profile(wl).astype("float32")).to(device)
+    a0 = beams.pump_for(wl, dtype=torch.complex64, device=device)
+    b0 = torch.zeros_like(a0)
+    w = torch.tensor([0.0, 1.0], dtype=torch.float64, device=device)
+    ws = plan.workspace(adjoint=True, device=device)
+
+    def run():
+        plan.adjoint(a0, b0, power_weights=w, temp=temp, want_t=True, workspace=ws)
+
+    run()
+    sec = _timed(run, reps, torch)
+    return {"workload": wl.name, "schedule": plan.describe(), "workspace_MB": round(ws.numel() / 2**20, 1),
+            "cell_steps": wl.cell_steps, "ms_per_fwd_adj": round(sec * 1e3, 3),
+            "cell_steps_per_s": round(wl.cell_steps / sec, 1)}
+
+
 FP64_MFMA_PEAK = 78.6e12
 
 
@@ -222,8 +248,8 @@ def lnl(device, steps=5):
 
 def run_all(device) -> dict:
     out = {}
-    for name, fn in (("batched", batched), ("fwd_adj", fwd_adj), ("lnl", lnl), ("thermal", thermal),
-                     ("self_consistent", self_consistent_loop)):
+    for name, fn in (("batched", batched), ("fwd_adj", fwd_adj), ("thermal_fwd_adj", thermal_fwd_adj),
+                     ("lnl", lnl), ("thermal", thermal), ("self_consistent", self_consistent_loop)):
         try:
             out[name] = fn(device)
         except Exception as exc:
