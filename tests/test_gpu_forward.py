@@ -345,3 +345,35 @@ def test_lnl_single_step_and_undepleted(dtype):
     parity(base.with_(nx=64, ny=64, nz=1, split="LNL"), dtype)
     parity(base.with_(nx=64, ny=64, nz=30, split="LNL", undepleted=True), dtype)
     parity(base.with_(nx=128, ny=32, nz=7, split="LNL", lx=base.lx / 2, ly=base.ly / 8), dtype)
+
+
+def test_power_trace_matches_oracle_and_one_shot_march():
+    """P(z) every 7 steps: the exit fields equal the one-shot march bit for bit,
+    every point matches the oracle's powers at that z, and without loss the
+    total P_F + P_SH is conserved along z (Manley-Rowe)."""
+    from paper_2410_04994_amd.trace import power_trace
+    wl = workloads.c2_plain_c64().with_(nx=64, ny=64, nz=40)
+    plan = make_plan(wl)
+    a0, b0 = inputs(wl)
+    a = torch.from_numpy(a0).cuda()
+    b = torch.from_numpy(b0).cuda()
+    z, pw = power_trace(plan, a, b, every=7)
+    full = run_gpu(plan, a0, b0)
+    assert np.array_equal(a.cpu().numpy(), full[0]) and np.array_equal(b.cpu().numpy(), full[1])
+    assert np.array_equal(pw[-1].cpu().numpy(), full[2])
+    ends = [7, 14, 21, 28, 35, 40]
+    assert np.allclose(z.cpu().numpy(), np.array(ends) * wl.lcr / wl.nz, rtol=0, atol=1e-15)
+    for i, s in enumerate(ends):
+        ref = run_oracle(wl, a0, b0, s_end=s)
+        got = pw[i].cpu().numpy()
+        assert abs(got[0] / ref["p_f"] - 1) < 1e-5 and abs(got[1] / ref["p_sh"] - 1) < 1e-5, s
+    lossless = wl.with_(alpha_f=0.0, alpha_sh=0.0, beta_f=0.0, beta_sh=0.0)
+    plan = make_plan(lossless)
+    a = torch.from_numpy(a0).cuda()
+    b = torch.from_numpy(b0).cuda()
+    _, pw = power_trace(plan, a, b, every=5)
+    tot = pw.sum(dim=1).cpu().numpy()
+    c = ssfm.coefficients(lossless.params())
+    p_in = ssfm.power(a0.astype(complex), lossless.n_f, c.dx, c.dy)
+    assert pw[-1, 1].item() > 1e-3 * p_in
+    assert np.max(np.abs(tot / p_in - 1)) < 1e-5
