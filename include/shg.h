@@ -63,7 +63,9 @@ enum {
   SHG_EUNSUPPORTED = 2, /* valid but not built here (e.g. grid size)        */
   SHG_ENOMEM = 3,       /* device allocation failed                          */
   SHG_EDEVICE = 4,      /* HIP runtime error, including earlier device faults */
-  SHG_ESTATE = 5        /* NULL or destroyed plan                            */
+  SHG_ESTATE = 5,       /* NULL or destroyed plan                            */
+  SHG_ENONFINITE = 6    /* SHG_CHECK_FINITE found NaN or Inf (message says
+                           which array, input or output)                     */
 };
 
 /* flags */
@@ -71,13 +73,19 @@ enum {
   SHG_UNDEPLETED = 1u << 0, /* undepleted pump: dA_F/dz has no nonlinear part */
   SHG_NO_GRAPH = 1u << 1,   /* launch passes one by one instead of replaying a
                                cached HIP graph of the whole march              */
-  SHG_SPLIT_LNL = 1u << 2   /* the other Strang order of Sec. 3, L/2 - N - L/2:
+  SHG_SPLIT_LNL = 1u << 2,  /* the other Strang order of Sec. 3, L/2 - N - L/2:
                                one RK4 over dz per step (stages at 0, dz/2, dz)
                                between two half-step propagators; interior
                                half-steps merge into one column pass.  Not with
                                shg_propagate_adjoint or shg_propagate_heat
                                (SHG_EUNSUPPORTED); all plans of a batch share
                                the order                                        */
+  SHG_CHECK_FINITE = 1u << 3 /* debugging aid: before a march, scan its input
+                               arrays (fields, dk_z, temperature, adjoint
+                               cotangents and weights) and after it the output
+                               fields for NaN or Inf; SHG_ENONFINITE names the
+                               array.  Each scan synchronises the stream (the
+                               scan kernels run before the march is enqueued)  */
 };
 
 typedef struct {

@@ -331,11 +331,28 @@ int propagate_adjoint(Plan& pl, const void* a_f_in, const void* a_sh_in, const d
     return fail(SHG_EUNSUPPORTED, "the adjoint covers the N/2 - L - N/2 split");
   int rc = sticky_device_error();
   if (rc) return rc;
+  const size_t field = 2 * (size_t)pl.p.nx * pl.p.ny;
+  if (checks_finite(pl)) {
+    if ((rc = check_finite(pl, a_f_in, field, false, "input a_f_in", st)) ||
+        (rc = check_finite(pl, a_sh_in, field, false, "input a_sh_in", st)) ||
+        (rc = check_finite(pl, dk_z, (size_t)pl.p.nz, true, "dk_z", st)) ||
+        (rc = check_finite(pl, temp, (size_t)pl.p.nz * field / 2, false, "temp", st)) ||
+        (rc = check_finite(pl, g_f_out, field, false, "g_f_out", st)) ||
+        (rc = check_finite(pl, g_sh_out, field, false, "g_sh_out", st)) ||
+        (rc = check_finite(pl, pw, 2, true, "power_weights", st)))
+      return rc;
+  }
   if (pl.dtype == SHG_C64)
-    return adjoint_t<float>(pl, a_f_in, a_sh_in, dk_z, temp, g_f_out, g_sh_out, pw, g_f_in,
-                            g_sh_in, g_dk, g_t, a_f_out, a_sh_out, powers, (char*)ws, st);
-  return adjoint_t<double>(pl, a_f_in, a_sh_in, dk_z, temp, g_f_out, g_sh_out, pw, g_f_in,
+    rc = adjoint_t<float>(pl, a_f_in, a_sh_in, dk_z, temp, g_f_out, g_sh_out, pw, g_f_in,
+                          g_sh_in, g_dk, g_t, a_f_out, a_sh_out, powers, (char*)ws, st);
+  else
+    rc = adjoint_t<double>(pl, a_f_in, a_sh_in, dk_z, temp, g_f_out, g_sh_out, pw, g_f_in,
                            g_sh_in, g_dk, g_t, a_f_out, a_sh_out, powers, (char*)ws, st);
+  if (rc || !checks_finite(pl)) return rc;
+  if ((rc = check_finite(pl, g_f_in, field, false, "the adjoint's output g_f_in", st)) ||
+      (rc = check_finite(pl, g_sh_in, field, false, "the adjoint's output g_sh_in", st)))
+    return rc;
+  return SHG_OK;
 }
 
 }  // namespace shg

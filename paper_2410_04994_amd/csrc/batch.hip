@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <tuple>
@@ -378,8 +379,8 @@ void free_batch(Plan& pl) {
   pl.batch = nullptr;
 }
 
-static int propagate_batch(int n, shg_plan* const* plans, void* const* a_f, void* const* a_sh,
-                           const double* const* dk_z, void* ws, double* powers, hipStream_t st) {
+static int run_batch(int n, shg_plan* const* plans, void* const* a_f, void* const* a_sh,
+                     const double* const* dk_z, void* ws, double* powers, hipStream_t st) {
   int rc = validate_batch(n, plans, a_f, a_sh);
   if (rc) return rc;
   if ((rc = sticky_device_error())) return rc;
@@ -491,6 +492,35 @@ static int propagate_batch(int n, shg_plan* const* plans, void* const* a_f, void
   }
   bc->key = key;
   return SHG_OK;
+}
+
+// run_batch with the SHG_CHECK_FINITE scans of the instances whose plans ask
+// for them: inputs before, output fields after.
+static int propagate_batch(int n, shg_plan* const* plans, void* const* a_f, void* const* a_sh,
+                           const double* const* dk_z, void* ws, double* powers, hipStream_t st) {
+  int rc = validate_batch(n, plans, a_f, a_sh);
+  if (rc) return rc;
+  auto scan = [&](bool inputs) {
+    char what[64];
+    for (int i = 0; i < n; ++i) {
+      Plan& pl = *reinterpret_cast<Plan*>(plans[i]);
+      if (!checks_finite(pl)) continue;
+      const size_t field = 2 * (size_t)pl.p.nx * pl.p.ny;
+      int r;
+      snprintf(what, sizeof what, "%s a_f[%d]", inputs ? "input" : "the march's output", i);
+      if ((r = check_finite(pl, a_f[i], field, false, what, st))) return r;
+      snprintf(what, sizeof what, "%s a_sh[%d]", inputs ? "input" : "the march's output", i);
+      if ((r = check_finite(pl, a_sh[i], field, false, what, st))) return r;
+      if (inputs && dk_z) {
+        snprintf(what, sizeof what, "dk_z[%d]", i);
+        if ((r = check_finite(pl, dk_z[i], (size_t)pl.p.nz, true, what, st))) return r;
+      }
+    }
+    return (int)SHG_OK;
+  };
+  if ((rc = scan(true))) return rc;
+  if ((rc = run_batch(n, plans, a_f, a_sh, dk_z, ws, powers, st))) return rc;
+  return scan(false);
 }
 
 }  // namespace shg

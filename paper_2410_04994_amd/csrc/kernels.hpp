@@ -389,6 +389,21 @@ __global__ void __launch_bounds__(256) psi_init(const R* __restrict__ temp, int 
   psi[i] = (R)acc;
 }
 
+// ---------------------------------------------------------------- finiteness scan
+// Debugging aid: flag[0] = 1 when any of the n values is NaN or infinite.  Only
+// lanes that find one store, all the same value; the flag is cleared first by
+// flag_clear on the same stream.
+template <typename T>
+__global__ void __launch_bounds__(256) finite_scan(const T* __restrict__ x, size_t n,
+                                                   int* __restrict__ flag) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    if (!isfinite(x[i])) flag[0] = 1;
+}
+
+static __global__ void __launch_bounds__(64) flag_clear(int* __restrict__ flag) {
+  if (threadIdx.x == 0) flag[0] = 0;
+}
+
 // ---------------------------------------------------------------- wide row pass
 // Latency-oriented row pass for marches that are too small to fill the chip:
 // every thread owns one cell (both fields) for the two RK4 half-steps, and the

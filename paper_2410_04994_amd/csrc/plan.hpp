@@ -59,6 +59,7 @@ struct Plan {
   size_t batch_ws_bytes = 0;
   // cached forward graph
   hipStream_t cap_stream = nullptr;
+  int* finite_flag = nullptr;  // device int of the SHG_CHECK_FINITE scans (allocated on first use)
   hipGraphExec_t gexec = nullptr;
   GraphKey gkey{};
   // optional per-kernel timing (kind 0 = row pass, 1 = column pass)
@@ -112,6 +113,11 @@ int ensure_own_ws(Plan& pl, size_t bytes);
 int propagate(Plan& pl, void* a_f, void* a_sh, const double* dk_z, const void* temp, int s0,
               int s1, void* ws, double* powers, hipStream_t st, void* heat);
 size_t align256(size_t v);
+// SHG_CHECK_FINITE: scan `count` reals of the plan's type (or doubles when dbl)
+// at `data` (NULL: nothing to scan); SHG_ENONFINITE names `what`.
+int check_finite(Plan& pl, const void* data, size_t count, bool dbl, const char* what,
+                 hipStream_t st);
+inline bool checks_finite(const Plan& pl) { return (pl.p.flags & SHG_CHECK_FINITE) != 0; }
 int launch_col(Plan& pl, void* a, void* b, int conj, hipStream_t st);
 bool row_supported(const Plan& pl, int e, int wg, int* rows);
 bool col_supported(const Plan& pl, int e, int tc);

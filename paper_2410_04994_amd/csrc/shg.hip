@@ -369,7 +369,7 @@ int validate_params(const shg_params* p) {
   if (p->checkpoint_every < 0) return fail(SHG_EINVAL, "checkpoint_every must be >= 0");
   if (!(std::fabs(p->walkoff_f) < M_PI / 2) || !(std::fabs(p->walkoff_sh) < M_PI / 2))
     return fail(SHG_EINVAL, "walk-off angles must be finite with |rho| < pi/2");
-  if (p->flags & ~(uint32_t)(SHG_UNDEPLETED | SHG_NO_GRAPH | SHG_SPLIT_LNL))
+  if (p->flags & ~(uint32_t)(SHG_UNDEPLETED | SHG_NO_GRAPH | SHG_SPLIT_LNL | SHG_CHECK_FINITE))
     return fail(SHG_EINVAL, "unknown flag bits 0x%x", p->flags);
   return SHG_OK;
 }
@@ -465,7 +465,7 @@ void free_plan_tables(Plan& pl) {
   pl.cap_stream = nullptr;
   void* ptrs[] = {pl.tw_x, pl.tw_y, pl.mx[0], pl.mx[1], pl.my[0], pl.my[1], pl.mxh[0], pl.mxh[1],
                   pl.myh[0], pl.myh[1], pl.own_ws,
-                  pl.batch_ws};
+                  pl.batch_ws, pl.finite_flag};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   pl.tw_x = pl.tw_y = nullptr;
@@ -473,6 +473,7 @@ void free_plan_tables(Plan& pl) {
   pl.mxh[0] = pl.mxh[1] = pl.myh[0] = pl.myh[1] = nullptr;
   pl.own_ws = nullptr;
   pl.batch_ws = nullptr;
+  pl.finite_flag = nullptr;
   free_adjoint(pl);
   free_batch(pl);
 }
@@ -767,6 +768,37 @@ int sticky_device_error() {
   return SHG_OK;
 }
 
+int check_finite(Plan& pl, const void* data, size_t count, bool dbl, const char* what,
+                 hipStream_t st) {
+  if (!data || count == 0) return SHG_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(st, &cs);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(SHG_EINVAL, "SHG_CHECK_FINITE scans synchronise the stream: not under capture");
+  if (!pl.finite_flag) {
+    e = hipMalloc(&pl.finite_flag, sizeof(int));
+    if (e != hipSuccess) {
+      pl.finite_flag = nullptr;
+      return hip_fail(e, "hipMalloc(finite flag)");
+    }
+  }
+  const dim3 grid((unsigned)std::min<size_t>(4096, (count + 255) / 256));
+  hipLaunchKernelGGL(flag_clear, dim3(1), dim3(64), 0, st, pl.finite_flag);
+  if (dbl || pl.dtype == SHG_C128)
+    hipLaunchKernelGGL((finite_scan<double>), grid, dim3(256), 0, st, (const double*)data, count,
+                       pl.finite_flag);
+  else
+    hipLaunchKernelGGL((finite_scan<float>), grid, dim3(256), 0, st, (const float*)data, count,
+                       pl.finite_flag);
+  int found = 0;
+  e = hipMemcpyAsync(&found, pl.finite_flag, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "finiteness scan");
+  if (found) return fail(SHG_ENONFINITE, "%s holds NaN or Inf", what);
+  return SHG_OK;
+}
+
 int propagate(Plan& pl, void* a_f, void* a_sh, const double* dk_z, const void* temp, int s0,
               int s1, void* ws, double* powers, hipStream_t st, void* heat) {
   if (!a_f || !a_sh) return fail(SHG_EINVAL, "a_f and a_sh must be non-NULL device pointers");
@@ -774,11 +806,24 @@ int propagate(Plan& pl, void* a_f, void* a_sh, const double* dk_z, const void* t
     return fail(SHG_EINVAL, "step range [%d, %d) not within [0, nz=%d]", s0, s1, pl.p.nz);
   int rc = sticky_device_error();
   if (rc) return rc;
+  const size_t field = 2 * (size_t)pl.p.nx * pl.p.ny;
+  if (checks_finite(pl)) {
+    if ((rc = check_finite(pl, a_f, field, false, "input a_f", st)) ||
+        (rc = check_finite(pl, a_sh, field, false, "input a_sh", st)) ||
+        (rc = check_finite(pl, dk_z, (size_t)pl.p.nz, true, "dk_z", st)) ||
+        (rc = check_finite(pl, temp, (size_t)pl.p.nz * field / 2, false, "temp", st)))
+      return rc;
+  }
   if (!ws) {
     if ((rc = ensure_own_ws(pl, forward_ws_bytes(pl)))) return rc;
     ws = pl.own_ws;
   }
-  return run_forward(pl, a_f, a_sh, dk_z, temp, s0, s1, ws, powers, st, heat);
+  rc = run_forward(pl, a_f, a_sh, dk_z, temp, s0, s1, ws, powers, st, heat);
+  if (rc || !checks_finite(pl)) return rc;
+  if ((rc = check_finite(pl, a_f, field, false, "the march's output a_f", st)) ||
+      (rc = check_finite(pl, a_sh, field, false, "the march's output a_sh", st)))
+    return rc;
+  return SHG_OK;
 }
 
 }  // namespace shg

@@ -94,6 +94,14 @@ def test_invalid_params_rejected_before_device(lib, bad, needle):
 def test_unknown_flags_and_dtype(lib):
     rc, _, msg = create(lib, good_params(), flags=1 << 7)
     assert rc == binding.SHG_EINVAL and "flag" in msg
+    # every documented flag passes validation (without a GPU the plan then
+    # fails later, at its first device allocation)
+    documented = (binding.SHG_UNDEPLETED | binding.SHG_NO_GRAPH | binding.SHG_SPLIT_LNL
+                  | binding.SHG_CHECK_FINITE)
+    rc, h, msg = create(lib, good_params(), flags=documented)
+    assert "flag" not in msg
+    if rc == binding.SHG_OK:
+        lib.shg_plan_destroy(h)
     rc, _, msg = create(lib, good_params(), dtype=7)
     assert rc == binding.SHG_EINVAL and "dtype" in msg
     cp = make_params(good_params())

@@ -377,3 +377,43 @@ def test_power_trace_matches_oracle_and_one_shot_march():
     p_in = ssfm.power(a0.astype(complex), lossless.n_f, c.dx, c.dy)
     assert pw[-1, 1].item() > 1e-3 * p_in
     assert np.max(np.abs(tot / p_in - 1)) < 1e-5
+
+
+def test_check_finite_flag_names_the_bad_array():
+    """SHG_CHECK_FINITE: NaN or Inf in an input is reported before the march
+    (naming the array), a march that overflows is reported after it, and clean
+    inputs give the same result as without the flag, bit for bit."""
+    from paper_2410_04994_amd import Plan, ShgError, propagate_batch
+    from paper_2410_04994_amd.binding import SHG_CHECK_FINITE
+    wl = workloads.c2_plain_c64().with_(nx=64, ny=64, nz=12)
+    plan = Plan(wl.params(), "c64", flags=SHG_CHECK_FINITE)
+    a0, b0 = inputs(wl)
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    a, b = dev(a0), dev(b0)
+    pw = plan.propagate(a, b)
+    ref = run_gpu(make_plan(wl), a0, b0)
+    assert np.array_equal(a.cpu().numpy(), ref[0]) and np.array_equal(b.cpu().numpy(), ref[1])
+    assert np.array_equal(pw.cpu().numpy(), ref[2])
+    bad = a0.copy()
+    bad[5, 7] = np.nan
+    with pytest.raises(ShgError, match="SHG_ENONFINITE.*input a_f"):
+        plan.propagate(dev(bad), dev(b0))
+    dk = np.full(wl.nz, wl.dk0)
+    dk[3] = np.inf
+    with pytest.raises(ShgError, match="SHG_ENONFINITE.*dk_z"):
+        plan.propagate(dev(a0), dev(b0), dk_z=dev(dk))
+    temp = np.full((wl.nz, 64, 64), wl.t_ref, np.float32)
+    temp[2, 1, 1] = np.nan
+    with pytest.raises(ShgError, match="SHG_ENONFINITE.*temp"):
+        plan.propagate(dev(a0), dev(b0), temp=dev(temp))
+    # a finite input so large that two-photon absorption overflows float
+    with pytest.raises(ShgError, match="SHG_ENONFINITE.*output"):
+        plan.propagate(dev(a0 * np.float32(1e19 / np.abs(a0).max())), dev(b0))
+    # the adjoint checks its cotangents, the batch each instance
+    g = np.zeros_like(a0)
+    g[0, 0] = np.inf
+    with pytest.raises(ShgError, match="SHG_ENONFINITE.*g_f_out"):
+        plan.adjoint(dev(a0), dev(b0), g_f_out=dev(g))
+    plans = [plan, Plan(wl.params(), "c64", flags=SHG_CHECK_FINITE)]
+    with pytest.raises(ShgError, match=r"SHG_ENONFINITE.*a_f\[1\]"):
+        propagate_batch(plans, [dev(a0), dev(bad)], [dev(b0), dev(b0)])
