@@ -151,16 +151,23 @@ def adjoint(p: dict, a_f0: np.ndarray, a_sh0: np.ndarray, g_f_out: np.ndarray,
     power_weights     : (w_F, w_SH) multiplying the exit powers in L
     Returns g_f, g_sh (gradients at z = 0), g_dk [nz] (per-step mismatch),
     g_temp [nz, ny, nx] when a temperature field is given, and the forward result."""
-    if ssfm.split_order(p) != "NLN":
-        raise NotImplementedError("the oracle adjoint covers the N/2 - L - N/2 split")
     c = ssfm.coefficients(p)
     dz = c.dz
     nz = p["nz"]
     und = bool(p.get("undepleted", False))
+    lnl = ssfm.split_order(p) == "LNL"
     fwd = ssfm.propagate(p, a_f0, a_sh0, dk_z, temp, return_states=True)
     rho_f, rho_sh = ssfm.walkoff_angles(p)
-    m_f = ssfm.propagator(p, c.k_f, p["alpha_f"], dz, rho_f)
-    m_sh = ssfm.propagator(p, c.k_sh, p["alpha_sh"], dz, rho_sh)
+    # the linear step of the split: L(dz) between the half-steps, or L(dz/2)
+    # on both sides of one RK4 over dz in the L/2 - N - L/2 order
+    hstep = dz / 2 if lnl else dz
+    m_f = ssfm.propagator(p, c.k_f, p["alpha_f"], hstep, rho_f)
+    m_sh = ssfm.propagator(p, c.k_sh, p["alpha_sh"], hstep, rho_sh)
+
+    def linear_adjoint(lam):
+        la = ssfm.linear_step(lam[0] + 1j * lam[1], np.conj(m_f))
+        lb = ssfm.linear_step(lam[2] + 1j * lam[3], np.conj(m_sh))
+        return _to_real(la, lb)
 
     cf = ssfm.EPS0 * ssfm.C_LIGHT * p["n_f"] / 2 * c.dx * c.dy
     cs = ssfm.EPS0 * ssfm.C_LIGHT * p["n_sh"] / 2 * c.dx * c.dy
@@ -183,20 +190,27 @@ def adjoint(p: dict, a_f0: np.ndarray, a_sh0: np.ndarray, g_f_out: np.ndarray,
         a, b = fwd["states"][s]
         dk_s, dT = ssfm.step_mismatch(p, s, dk_z, temp)
         phi0 = phis[s]
-        # recompute the forward stages of step s
-        y0 = _to_real(a, b)
-        y1, _ = rk4_forward_stages(y0, phi0, dk_s, 0.0, dz / 2, dT, c, und)
-        a1 = ssfm.linear_step(y1[0] + 1j * y1[1], m_f)
-        b1 = ssfm.linear_step(y1[2] + 1j * y1[3], m_sh)
-        y2 = _to_real(a1, b1)
-        # second half-step
-        lam, gp2, gpt2, gT2 = rk4_reverse(y2, lam, phi0, dk_s, dz / 2, dz / 2, dT, c, und)
-        # linear step (complex-linear, adjoint uses conj(M))
-        la = ssfm.linear_step(lam[0] + 1j * lam[1], np.conj(m_f))
-        lb = ssfm.linear_step(lam[2] + 1j * lam[3], np.conj(m_sh))
-        lam = _to_real(la, lb)
-        # first half-step
-        lam, gp1, gpt1, gT1 = rk4_reverse(y0, lam, phi0, dk_s, 0.0, dz / 2, dT, c, und)
+        if lnl:
+            # step s: y0 -> L(dz/2) -> RK4 over [z_s, z_s + dz] -> L(dz/2)
+            v = _to_real(ssfm.linear_step(a, m_f), ssfm.linear_step(b, m_sh))
+            lam = linear_adjoint(lam)
+            lam, gp1, gpt1, gT1 = rk4_reverse(v, lam, phi0, dk_s, 0.0, dz, dT, c, und)
+            lam = linear_adjoint(lam)
+            gp2 = gpt2 = 0.0
+            gT2 = 0.0
+        else:
+            # recompute the forward stages of step s
+            y0 = _to_real(a, b)
+            y1, _ = rk4_forward_stages(y0, phi0, dk_s, 0.0, dz / 2, dT, c, und)
+            a1 = ssfm.linear_step(y1[0] + 1j * y1[1], m_f)
+            b1 = ssfm.linear_step(y1[2] + 1j * y1[3], m_sh)
+            y2 = _to_real(a1, b1)
+            # second half-step
+            lam, gp2, gpt2, gT2 = rk4_reverse(y2, lam, phi0, dk_s, dz / 2, dz / 2, dT, c, und)
+            # linear step (complex-linear, adjoint uses conj(M))
+            lam = linear_adjoint(lam)
+            # first half-step
+            lam, gp1, gpt1, gT1 = rk4_reverse(y0, lam, phi0, dk_s, 0.0, dz / 2, dT, c, und)
         g_phi_s = gp1 + gp2
         g_dk_direct = gpt1 + gpt2
         g_dk_s = g_dk_direct + dz * acc_phi

@@ -36,11 +36,13 @@ def loss(p, a, b, g_f, g_sh, w, dk_z=None, temp=None):
             + w[0] * out["p_f"] + w[1] * out["p_sh"])
 
 
-@pytest.mark.parametrize("with_temp,undepleted,walkoff,cubic", [
-    (False, False, 0.0, False), (True, False, 0.0, False), (True, True, 0.0, False),
-    (False, False, 0.02, False), (True, False, 0.0, True)])
-def test_adjoint_matches_central_differences(with_temp, undepleted, walkoff, cubic):
-    p = params(undepleted=undepleted, walkoff_sh=walkoff, walkoff_f=-0.5 * walkoff)
+@pytest.mark.parametrize("with_temp,undepleted,walkoff,cubic,split", [
+    (False, False, 0.0, False, "NLN"), (True, False, 0.0, False, "NLN"),
+    (True, True, 0.0, False, "NLN"), (False, False, 0.02, False, "NLN"),
+    (True, False, 0.0, True, "NLN"), (False, False, 0.02, False, "LNL"),
+    (True, False, 0.0, True, "LNL")])
+def test_adjoint_matches_central_differences(with_temp, undepleted, walkoff, cubic, split):
+    p = params(undepleted=undepleted, walkoff_sh=walkoff, walkoff_f=-0.5 * walkoff, split=split)
     if cubic:
         # cubic dispersion part and a grating period with an exaggerated expansion
         p.update(ddk_dT2=-120.0, ddk_dT3=45.0, grating_period=8e-6, grating_a=2e-3, grating_b=-4e-5)
