@@ -77,9 +77,8 @@ enum {
                                one RK4 over dz per step (stages at 0, dz/2, dz)
                                between two half-step propagators; interior
                                half-steps merge into one column pass.  Not with
-                               shg_propagate_adjoint or shg_propagate_heat
-                               (SHG_EUNSUPPORTED); all plans of a batch share
-                               the order                                        */
+                               shg_propagate_heat (SHG_EUNSUPPORTED); all plans
+                               of a batch share the order                       */
   SHG_CHECK_FINITE = 1u << 3 /* debugging aid: before a march, scan its input
                                arrays (fields, dk_z, temperature, adjoint
                                cotangents and weights) and after it the output

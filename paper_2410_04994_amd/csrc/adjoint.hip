@@ -1,5 +1,8 @@
 // shg_propagate_adjoint: checkpointed reverse march.
 //
+// (The L/2 - N - L/2 order stages the state entering each step's RK4 and runs
+// the mirrored sequence; see the backward sweep.)
+//
 // Forward sweep: the march runs in segments of K steps; the real-space state at
 // the start of every segment is kept (checkpoints).  Backward sweep, segment by
 // segment from the exit: the segment is recomputed from its checkpoint with the
@@ -252,7 +255,59 @@ static int adjoint_t(Plan& pl, const void* a_f_in, const void* a_sh_in, const do
   };
   auto spsi = [&](int s, int b) { return psi_stage + (size_t)(s - b) * n2; };
   int rows = 1;
-  for (int k = L.segs - 1; k >= 0; --k) {
+  const bool lnl = (p.flags & SHG_SPLIT_LNL) != 0;
+  ra.full = lnl ? 1 : 0;
+  for (int k = L.segs - 1; k >= 0 && lnl; --k) {
+    // L/2 - N - L/2: a segment [b, e) runs FFT_x, a half-step column pass, per
+    // step s the row pass IFFT_x . RK4 over dz . FFT_x and a column pass (the
+    // half-step one after the last step), and IFFT_x.  Its pull-back, in
+    // reverse: FFT_x; conj(M_half); per step s = e-1 .. b the adjoint row pass
+    // of s (from the staged RK4 input) and conj(M) of the column pass before s
+    // (the half-step one for s = b); IFFT_x.
+    const int b = k * L.k, e = std::min(p.nz, b + L.k);
+    const void *ia, *ib;
+    seg_in(k, &ia, &ib);
+    if (k < L.segs - 1) {
+      FwdIO io{ia, ib, work, work + n2, work, work + n2, stage};
+      if (th) {
+        hipLaunchKernelGGL((copy_real<R>), dim3(nb), dim3(256), 0, st, (const R*)psi_ck(k),
+                           psi_work, n2);
+        io.temp = temp;
+        io.psi = psi_work;
+        io.tap_psi = psi_stage;
+      }
+      rc = enqueue_forward_io(pl, io, dk_z, b, e, fws, nullptr, st, false);
+      if (rc) return rc;
+    }
+    ra.ua = staged(e - 1, b);
+    ra.ub = staged(e - 1, b) + n2;
+    ra.s_second = ra.s_first = -1;
+    ra.inv_in = 0;
+    ra.fwd_out = 1;
+    ra.gp_first = ra.gp_second = nullptr;
+    if (!adj(ra, spsi(e - 1, b), &rows))
+      return fail(SHG_EUNSUPPORTED, "adjoint row schedule e=%d wg=%d not built", pl.adj_e,
+                  pl.adj_wg);
+    if ((rc = launch_col(pl, la, lb, 1, st, true))) return rc;
+    for (int s = e - 1; s >= b; --s) {
+      ra.ua = staged(s, b);
+      ra.ub = staged(s, b) + n2;
+      ra.s_first = s;
+      ra.inv_in = 1;
+      ra.fwd_out = 1;
+      ra.gp_first = g1(s);
+      adj(ra, spsi(s, b), &rows);
+      if ((rc = launch_col(pl, la, lb, 1, st, s == b))) return rc;
+    }
+    ra.ua = (const cx<R>*)ia;
+    ra.ub = (const cx<R>*)ib;
+    ra.s_first = -1;
+    ra.inv_in = 1;
+    ra.fwd_out = 0;
+    ra.gp_first = nullptr;
+    adj(ra, th ? psi_ck(k) : nullptr, &rows);
+  }
+  for (int k = L.segs - 1; k >= 0 && !lnl; --k) {
     const int b = k * L.k, e = std::min(p.nz, b + L.k);
     const void *ia, *ib;
     seg_in(k, &ia, &ib);
@@ -309,7 +364,7 @@ static int adjoint_t(Plan& pl, const void* a_f_in, const void* a_sh_in, const do
   }
   if (g_dk) {
     hipLaunchKernelGGL(grad_step_sums, dim3(p.nz), dim3(256), 0, st, (const double*)gp1,
-                       (const double*)gp2, p.ny / rows, gh);
+                       lnl ? nullptr : (const double*)gp2, p.ny / rows, gh);
     hipLaunchKernelGGL(grad_dk_finalize, dim3(1), dim3(256), 0, st, (const double*)gh, p.nz,
                        pl.dz, g_dk);
   }
@@ -327,8 +382,6 @@ int propagate_adjoint(Plan& pl, const void* a_f_in, const void* a_sh_in, const d
   if (!g_f_in || !g_sh_in) return fail(SHG_EINVAL, "g_f_in and g_sh_in must be non-NULL");
   if (!ws) return fail(SHG_EINVAL, "workspace must be non-NULL (shg_workspace_bytes(plan, 1))");
   if (g_t && !temp) return fail(SHG_EINVAL, "g_t_moments requires a temperature field");
-  if (pl.p.flags & SHG_SPLIT_LNL)
-    return fail(SHG_EUNSUPPORTED, "the adjoint covers the N/2 - L - N/2 split");
   int rc = sticky_device_error();
   if (rc) return rc;
   const size_t field = 2 * (size_t)pl.p.nx * pl.p.ny;

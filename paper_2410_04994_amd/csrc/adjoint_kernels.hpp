@@ -110,6 +110,7 @@ struct RowAdjArgs {
   int s_first;            // step whose first half-step is pulled back, or -1
   int inv_in;             // lambda arrives in the (q_x, y) domain: apply IFFT_x on load
   int fwd_out;            // apply FFT_x before storing (lambda leaves in the (q_x, y) domain)
+  int full;               // s_first is a whole step over 2h (L/2 - N - L/2 order)
   R kf, ks, tf, ts, h;
   int undepleted;
 };
@@ -170,11 +171,11 @@ static __global__ void __launch_bounds__(256) grad_step_sums(const double* __res
   __shared__ double red[8];
   const int s = blockIdx.x;
   const double* f = first + (size_t)s * nblk * 2;
-  const double* q = second + (size_t)s * nblk * 2;
+  const double* q = second ? second + (size_t)s * nblk * 2 : nullptr;   // null: one pass per step
   double x = 0.0, y = 0.0;
   for (int i = threadIdx.x; i < nblk; i += 256) {
-    x += f[2 * i] + q[2 * i];
-    y += f[2 * i + 1] + q[2 * i + 1];
+    x += f[2 * i] + (q ? q[2 * i] : 0.0);
+    y += f[2 * i + 1] + (q ? q[2 * i + 1] : 0.0);
   }
   block_sum2<256>(x, y, red);
   if (threadIdx.x == 0) {
@@ -323,7 +324,7 @@ __device__ __forceinline__ AdjPre<R, TH> adj_load(const RowAdjArgs<R>& p, const 
   a.ua = p.ua[idx];
   a.ub = p.ub[idx];
   if constexpr (!TH) {
-    if (p.s_first >= 0) a.c1 = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks);
+    if (p.s_first >= 0) a.c1 = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, p.full ? 2 : 1);
     if (p.s_second >= 0) a.c2 = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);
   } else {
     a.psi = q.psi[idx];
@@ -349,7 +350,7 @@ __device__ __forceinline__ void adj_cell(const RowAdjArgs<R>& p, const RowAdjTAr
     if (p.s_second >= 0) rk4_cell(ya, yb, c2, p.tf, p.ts, h, und);
     R g = 0, gt = 0;
     if (p.s_first >= 0) {
-      rk4_vjp(ya, yb, la, lb, c1, p.tf, p.ts, h, und, (R)0, g, gt);
+      rk4_vjp(ya, yb, la, lb, c1, p.tf, p.ts, p.full ? h + h : h, und, (R)0, g, gt);
       acc[0] += (double)g;
       acc[1] += (double)gt;
     }
@@ -375,11 +376,13 @@ __device__ __forceinline__ void adj_cell(const RowAdjArgs<R>& p, const RowAdjTAr
     }
     if (p.s_first >= 0) {
       const R dT = pre.dT1;
+      const int st = p.full ? 2 : 1;
       const HalfStepT<R> c1 = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, psi,
-                                            thermal_dk(dT, q.dk), dT, (R)0, qdz,
-                                            q.lens_f, q.lens_sh);
+                                            thermal_dk(dT, q.dk), dT, (R)0, qdz * (R)st,
+                                            q.lens_f, q.lens_sh, st);
       R g = 0, gt = 0, gl = 0;
-      rk4_vjp_t(ya, yb, la, lb, c1, p.tf, p.ts, q.lens_f, q.lens_sh, h, und, (R)0, g, gt, gl);
+      rk4_vjp_t(ya, yb, la, lb, c1, p.tf, p.ts, q.lens_f, q.lens_sh, h * (R)st, und, (R)0, g, gt,
+                gl);
       acc[0] += (double)g;
       acc[1] += (double)gt;
       // step s_first is complete: its second half-step was pulled back earlier

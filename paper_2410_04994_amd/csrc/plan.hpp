@@ -118,7 +118,9 @@ size_t align256(size_t v);
 int check_finite(Plan& pl, const void* data, size_t count, bool dbl, const char* what,
                  hipStream_t st);
 inline bool checks_finite(const Plan& pl) { return (pl.p.flags & SHG_CHECK_FINITE) != 0; }
-int launch_col(Plan& pl, void* a, void* b, int conj, hipStream_t st);
+// Column pass over the fields a, b with the plan's propagator (conj: conj(M);
+// half: the half-step tables of the L/2 - N - L/2 order).
+int launch_col(Plan& pl, void* a, void* b, int conj, hipStream_t st, bool half = false);
 bool row_supported(const Plan& pl, int e, int wg, int* rows);
 bool col_supported(const Plan& pl, int e, int tc);
 

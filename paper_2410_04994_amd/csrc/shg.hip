@@ -581,9 +581,15 @@ static int enqueue_forward_t(Plan& pl, const FwdIO& io, const double* dk_z, int 
     ra.inv_in = 1;
     for (int s = s0; s < s1; ++s) {
       ra.s_first = s;
+      // staging for the adjoint: the real-space state entering step s's RK4
+      ra.tap_a = tap ? tap + (size_t)(s - s0) * 2 * n2 : nullptr;
+      ra.tap_b = tap ? tap + (size_t)(s - s0) * 2 * n2 + n2 : nullptr;
+      ra.tap_psi = tap_psi ? tap_psi + (size_t)(s - s0) * n2 : nullptr;
       row_dispatch<R>(p.nx, pl.row_e, pl.row_wg, &ra, st, &rows, &tm);
       col_dispatch<R>(p.ny, pl.col_e, pl.col_tc, s == s1 - 1 ? &ch : &ca, st, &tm);
     }
+    ra.tap_a = ra.tap_b = nullptr;
+    ra.tap_psi = nullptr;
     ra.s_first = -1;
     ra.fwd_out = 0;
     ra.aout = (cx<R>*)io.a_out;
@@ -647,7 +653,10 @@ int enqueue_forward_io(Plan& pl, const FwdIO& io, const double* dk_z, int s0, in
   return enqueue_forward_t<double>(pl, io, dk_z, s0, s1, (char*)ws, powers, st, make_phase);
 }
 
-int launch_col(Plan& pl, void* a, void* b, int conj, hipStream_t st) {
+int launch_col(Plan& pl, void* a, void* b, int conj, hipStream_t st, bool half) {
+  if (half && !pl.mxh[0]) return fail(SHG_ESTATE, "no half-step propagator tables");
+  const double* const* mx = half ? pl.mxh : pl.mx;
+  const double* const* my = half ? pl.myh : pl.my;
   bool okk;
   if (pl.dtype == SHG_C64) {
     ColArgs<float> ca{};
@@ -655,8 +664,8 @@ int launch_col(Plan& pl, void* a, void* b, int conj, hipStream_t st) {
     ca.f[1] = (cx<float>*)b;
     ca.tw = (const Tw<float>*)pl.tw_y;
     for (int w = 0; w < 2; ++w) {
-      ca.mx[w] = pl.mx[w];
-      ca.my[w] = pl.my[w];
+      ca.mx[w] = mx[w];
+      ca.my[w] = my[w];
     }
     ca.nx = pl.p.nx;
     ca.tiles = pl.p.nx / pl.col_tc;
@@ -668,8 +677,8 @@ int launch_col(Plan& pl, void* a, void* b, int conj, hipStream_t st) {
     ca.f[1] = (cx<double>*)b;
     ca.tw = (const Tw<double>*)pl.tw_y;
     for (int w = 0; w < 2; ++w) {
-      ca.mx[w] = pl.mx[w];
-      ca.my[w] = pl.my[w];
+      ca.mx[w] = mx[w];
+      ca.my[w] = my[w];
     }
     ca.nx = pl.p.nx;
     ca.tiles = pl.p.nx / pl.col_tc;

@@ -305,3 +305,51 @@ def test_full_size_thermal_scalar_gradients_against_central_differences():
           flush=True)
     assert abs(t0.grad.item() - fd_t0) <= 1e-3 * abs(fd_t0)
     assert abs(sc.grad.item() - fd_sc) <= 1e-3 * abs(fd_sc)
+
+
+@pytest.mark.parametrize("dtype,tol,ckpt,thermal", [("c128", 1e-10, 0, False), ("c128", 1e-10, 4, False),
+                                                   ("c64", 1e-4, 5, False), ("c128", 1e-10, 5, True),
+                                                   ("c64", 1e-4, 0, True)])
+def test_lnl_adjoint_matches_oracle(dtype, tol, ckpt, thermal):
+    """The L/2 - N - L/2 order: reverse of L(dz/2), one RK4 over dz, L(dz/2)
+    per step, with walk-off, a per-step mismatch profile and (thermal) a
+    temperature field with the full dk(T); ckpt > 0 recomputes segments from
+    checkpoints, whose boundaries split a merged column pass into two halves."""
+    from paper_2410_04994_amd import Plan
+    if thermal:
+        wl, temp = thermal_small(nz=18)
+        wl = wl.with_(split="LNL", **CUBIC_DK)
+    else:
+        wl, a0, b0, gf, gs, w, dk = small_case(nz=17)
+        base = workloads.c2_plain_c64()
+        wl = wl.with_(split="LNL", walkoff_sh=0.05 * base.lx / base.lcr)
+        temp = None
+    rng = np.random.Generator(np.random.PCG64(12))
+    a0, b0 = inputs(wl, "c128")
+    a0 = a0.astype(complex)
+    b0 = (0.05 * np.abs(a0).max() * (rng.normal(size=a0.shape) + 1j * rng.normal(size=a0.shape)))
+    scale = 1.0 / np.abs(a0).max()
+    gf = (rng.normal(size=a0.shape) + 1j * rng.normal(size=a0.shape)) * scale
+    gs = (rng.normal(size=a0.shape) + 1j * rng.normal(size=a0.shape)) * scale
+    dk = wl.dk0 + 300.0 * rng.normal(size=wl.nz)
+    w = (0.3, 2.0)
+    rdt = np.float32 if dtype == "c64" else np.float64
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    if temp is not None:
+        temp = temp.astype(rdt)
+    a0, b0, gf, gs = (x.astype(npdt).astype(complex) for x in (a0, b0, gf, gs))
+    ref = oadj.adjoint(wl.params(), a0, b0, gf, gs, dk_z=dk,
+                       temp=None if temp is None else temp.astype(np.float64), power_weights=w)
+    plan = Plan(wl.params(), dtype, checkpoint_every=ckpt)
+    res = plan.adjoint(cuda(a0.astype(npdt)), cuda(b0.astype(npdt)), g_f_out=cuda(gf.astype(npdt)),
+                       g_sh_out=cuda(gs.astype(npdt)), power_weights=cuda(np.asarray(w)),
+                       dk_z=cuda(dk), temp=None if temp is None else cuda(temp), want_dk=True,
+                       want_t=temp is not None)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in res.items()}
+    assert rel(got["g_f"], ref["g_f"]) < tol
+    assert rel(got["g_sh"], ref["g_sh"]) < tol
+    assert rel(got["g_dk"], ref["g_dk"]) < tol
+    assert rel(got["a_sh"], ref["forward"]["a_sh"]) < tol
+    if temp is not None:
+        assert rel(got["g_t_moments"], ref["g_t_moments"]) < tol

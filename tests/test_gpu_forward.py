@@ -327,14 +327,14 @@ def test_lnl_with_temperature_field_and_resume(dtype, dk_t):
     assert rel(rest[1], full[1]) < (1e-5 if dtype == "c64" else 1e-12)
 
 
-def test_lnl_refuses_adjoint_and_heat_output():
+def test_lnl_refuses_heat_output():
+    """The heat source is written between the half-steps of the N/2 - L - N/2
+    order; in the L/2 - N - L/2 order no pass holds a step boundary in real space."""
     from paper_2410_04994_amd import ShgError
     wl = workloads.c2_plain_c64().with_(nx=32, ny=32, nz=4, split="LNL")
     plan = make_plan(wl)
     a = torch.ones((32, 32), dtype=torch.complex64, device="cuda")
     b = torch.zeros_like(a)
-    with pytest.raises(ShgError, match="SHG_EUNSUPPORTED"):
-        plan.adjoint(a, b, power_weights=torch.tensor([0.0, 1.0], dtype=torch.float64, device="cuda"))
     with pytest.raises(ShgError, match="SHG_EUNSUPPORTED"):
         plan.propagate_heat(a, b)
 
