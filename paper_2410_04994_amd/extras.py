@@ -219,7 +219,8 @@ def self_consistent_loop(device):
 
 def lnl(device, steps=5):
     """The L/2 - N - L/2 order (one RK4 over dz per step): the 256 x 256 x 1000
-    march and the batched sweep, to compare with the N/2 - L - N/2 lines."""
+    march, the batched sweep and the forward + adjoint of the differentiation
+    workload, to compare with the N/2 - L - N/2 lines."""
     import torch
     import workloads
     from paper_2410_04994_amd import Plan, beams, autotune
@@ -243,6 +244,24 @@ def lnl(device, steps=5):
                       "cell_steps_per_s": round(wl.cell_steps / sec, 1)}}
     res = batched(device, split="LNL")
     out["batched"] = {k: res[k] for k in ("ms_per_sweep", "cell_steps_per_s", "frac_hbm_at_64B")}
+    # forward + adjoint of the differentiation workload in this order
+    wd = workloads.c4_diff_c64().with_(split="LNL")
+    pd = Plan(wd.params(), "c64")
+    autotune.tune_single(pd)
+    a0 = beams.pump_for(wd, theta=torch.from_numpy(workloads.phase_noise(wd)).to(device),
+                        dtype=torch.complex64, device=device)
+    b0 = torch.zeros_like(a0)
+    dk = torch.full((wd.nz,), wd.dk0, dtype=torch.float64, device=device)
+    w = torch.tensor([0.0, 1.0], dtype=torch.float64, device=device)
+    wsa = pd.workspace(adjoint=True, device=device)
+
+    def run_adj():
+        pd.adjoint(a0, b0, power_weights=w, dk_z=dk, want_dk=True, workspace=wsa)
+
+    run_adj()
+    sec = _timed(run_adj, 2, torch)
+    out["fwd_adj"] = {"workload": wd.name + "_lnl", "ms_per_fwd_adj": round(sec * 1e3, 3),
+                      "cell_steps_per_s": round(wd.cell_steps / sec, 1)}
     return out
 
 
