@@ -280,18 +280,33 @@ class Plan:
         return heat, powers
 
     def adjoint(self, a_f_in, a_sh_in, g_f_out=None, g_sh_out=None, power_weights=None, dk_z=None,
-                temp=None, want_dk=False, want_t=False, workspace=None, stream=None):
+                temp=None, want_dk=False, want_t=False, workspace=None, stream=None, out=None):
         """Forward + reverse march.  Returns a dict with g_f, g_sh (gradients at
-        z = 0), a_f, a_sh (exit fields), powers, and g_dk / g_t_moments if asked."""
+        z = 0), a_f, a_sh (exit fields), powers, and g_dk / g_t_moments if asked.
+        out: optional dict of preallocated outputs under the same keys."""
         torch = _torch()
         dev = a_f_in.device
-        g_f = torch.empty_like(a_f_in)
-        g_sh = torch.empty_like(a_sh_in)
-        a_f = torch.empty_like(a_f_in)
-        a_sh = torch.empty_like(a_sh_in)
-        powers = torch.empty(2, dtype=torch.float64, device=dev)
-        g_dk = torch.empty(self.params["nz"], dtype=torch.float64, device=dev) if want_dk else None
-        g_t = torch.empty(2, dtype=torch.float64, device=dev) if want_t else None
+        out = out or {}
+        g_f = out.get("g_f", None)
+        g_f = torch.empty_like(a_f_in) if g_f is None else g_f
+        g_sh = out.get("g_sh", None)
+        g_sh = torch.empty_like(a_sh_in) if g_sh is None else g_sh
+        a_f = out.get("a_f", None)
+        a_f = torch.empty_like(a_f_in) if a_f is None else a_f
+        a_sh = out.get("a_sh", None)
+        a_sh = torch.empty_like(a_sh_in) if a_sh is None else a_sh
+        powers = out.get("powers", None)
+        powers = torch.empty(2, dtype=torch.float64, device=dev) if powers is None else powers
+        g_dk = out.get("g_dk", None)
+        if want_dk and g_dk is None:
+            g_dk = torch.empty(self.params["nz"], dtype=torch.float64, device=dev)
+        g_t = out.get("g_t_moments", None)
+        if want_t and g_t is None:
+            g_t = torch.empty(2, dtype=torch.float64, device=dev)
+        if not want_dk:
+            g_dk = None
+        if not want_t:
+            g_t = None
         if workspace is None:
             workspace = self.workspace(adjoint=True, device=dev)
         _check(load_library().shg_propagate_adjoint(

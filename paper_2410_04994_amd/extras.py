@@ -17,6 +17,15 @@ def _timed(fn, reps, torch):
     return (time.perf_counter() - t) / reps
 
 
+def _adjoint_outputs(a, nz, torch):
+    """Output buffers kept across timed adjoint calls (no allocation in the
+    timed region)."""
+    return {"g_f": torch.empty_like(a), "g_sh": torch.empty_like(a), "a_f": torch.empty_like(a),
+            "a_sh": torch.empty_like(a), "powers": torch.empty(2, dtype=torch.float64, device=a.device),
+            "g_dk": torch.empty(nz, dtype=torch.float64, device=a.device),
+            "g_t_moments": torch.empty(2, dtype=torch.float64, device=a.device)}
+
+
 def batched(device, reps=3, split="NLN"):
     import torch
     import workloads
@@ -60,8 +69,10 @@ def fwd_adj(device, reps=2):
     w = torch.tensor([0.0, 1.0], dtype=torch.float64, device=device)
     ws = plan.workspace(adjoint=True, device=device)
 
+    out = _adjoint_outputs(a0, wl.nz, torch)
+
     def run():
-        plan.adjoint(a0, b0, power_weights=w, dk_z=dk, want_dk=True, workspace=ws)
+        plan.adjoint(a0, b0, power_weights=w, dk_z=dk, want_dk=True, workspace=ws, out=out)
 
     run()
     sec = _timed(run, reps, torch)
@@ -75,7 +86,7 @@ def fwd_adj(device, reps=2):
     ws32 = plan32.workspace(adjoint=True, device=device)
 
     def run32():
-        plan32.adjoint(a0, b0, power_weights=w, dk_z=dk, want_dk=True, workspace=ws32)
+        plan32.adjoint(a0, b0, power_weights=w, dk_z=dk, want_dk=True, workspace=ws32, out=out)
 
     run32()
     sec32 = _timed(run32, reps, torch)
@@ -102,8 +113,10 @@ def thermal_fwd_adj(device, reps=2):
     w = torch.tensor([0.0, 1.0], dtype=torch.float64, device=device)
     ws = plan.workspace(adjoint=True, device=device)
 
+    out = _adjoint_outputs(a0, wl.nz, torch)
+
     def run():
-        plan.adjoint(a0, b0, power_weights=w, temp=temp, want_t=True, workspace=ws)
+        plan.adjoint(a0, b0, power_weights=w, temp=temp, want_t=True, workspace=ws, out=out)
 
     run()
     sec = _timed(run, reps, torch)
@@ -255,8 +268,10 @@ def lnl(device, steps=5):
     w = torch.tensor([0.0, 1.0], dtype=torch.float64, device=device)
     wsa = pd.workspace(adjoint=True, device=device)
 
+    out_adj = _adjoint_outputs(a0, wd.nz, torch)
+
     def run_adj():
-        pd.adjoint(a0, b0, power_weights=w, dk_z=dk, want_dk=True, workspace=wsa)
+        pd.adjoint(a0, b0, power_weights=w, dk_z=dk, want_dk=True, workspace=wsa, out=out_adj)
 
     run_adj()
     sec = _timed(run_adj, 2, torch)

@@ -353,3 +353,22 @@ def test_lnl_adjoint_matches_oracle(dtype, tol, ckpt, thermal):
     assert rel(got["a_sh"], ref["forward"]["a_sh"]) < tol
     if temp is not None:
         assert rel(got["g_t_moments"], ref["g_t_moments"]) < tol
+
+
+
+def test_adjoint_into_caller_buffers():
+    """Outputs written into caller-provided buffers equal those of a call that
+    allocates them."""
+    from paper_2410_04994_amd import Plan
+    wl = small_case(nz=8)[0]
+    plan = Plan(wl.params(), "c64")
+    a0, b0 = inputs(wl, "c64")
+    a, b = cuda(a0), cuda(b0)
+    w = cuda(np.array([0.2, 1.0]))
+    ref = plan.adjoint(a, b, power_weights=w, want_dk=True)
+    out = {k: torch.empty_like(v) for k, v in ref.items()}
+    got = plan.adjoint(a, b, power_weights=w, want_dk=True, out=out)
+    torch.cuda.synchronize()
+    for k in ref:
+        assert got[k].data_ptr() == out[k].data_ptr()
+        assert torch.equal(got[k], ref[k]), k
