@@ -94,8 +94,9 @@ def main(argv=None):
                          "(reference for the HBM byte counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(independent instances shard across GPUs with no exchange; see the design notes)",
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: a single march "
+              "does not shard (two all-to-alls per z-step would outweigh the step), and "
+              "independent instances would shard by instance with no exchange",
               file=sys.stderr)
         return 2
 

@@ -9,8 +9,8 @@ Model (Sec. 2.1, Eqs. 1-4; Sec. 3, Eqs. 11-15; Appendix A, Eqs. A.1-A.5):
   dA_SH/dz = i kSH e^{+i phi} A_F^2       - (i/2k_SH) lap A_SH - (alpha_SH/2) A_SH
              - (beta~_SH/2)|A_SH|^2 A_SH - i g_SH dT A_SH
 
-Readings of the printed equations (each is listed with its justification in
-the design notes and pinned by a test in tests/test_oracle_pins.py):
+Readings of the printed equations (each is pinned by a test in
+tests/test_oracle_pins.py):
   * coupling: kF = 2 pi d/(n_F lambda_F); kSH = 2 pi d/(n_SH lambda_F).  The
     printed SH coefficient uses lambda_SH, which breaks Manley-Rowe energy
     conservation with the intensity I = eps0 c n |A|^2 / 2 of Sec. 2.2 and gives

@@ -3,7 +3,9 @@
     python -m paper_2410_04994_amd.build          (or __graft_entry__.build())
 
 Sources are compiled to objects in parallel, then linked.  Packed-FP32 VALU
-instructions are disabled for all device code (see the design notes)."""
+instructions are disabled for all device code: hipcc would otherwise form
+them from ordinary float code, and some of their forms have returned wrong
+results on this hardware without any error."""
 from __future__ import annotations
 
 import concurrent.futures as cf
