@@ -4,8 +4,8 @@
 
 Sources are compiled to objects in parallel, then linked.  Packed-FP32 VALU
 instructions are disabled for all device code: hipcc would otherwise form
-them from ordinary float code, and some of their forms have returned wrong
-results on this hardware without any error."""
+them from ordinary float code, and some of their forms are known to give
+wrong results now and then, without any error."""
 from __future__ import annotations
 
 import concurrent.futures as cf
