@@ -417,3 +417,50 @@ def test_check_finite_flag_names_the_bad_array():
     plans = [plan, Plan(wl.params(), "c64", flags=SHG_CHECK_FINITE)]
     with pytest.raises(ShgError, match=r"SHG_ENONFINITE.*a_f\[1\]"):
         propagate_batch(plans, [dev(a0), dev(bad)], [dev(b0), dev(b0)])
+
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256, 512])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_transforms_on_white_noise(n, dtype):
+    """The linear step alone (d_eff = 0, no two-photon absorption) on white-noise
+    fields, which fill every frequency bin: two steps are IFFT(M FFT(.)) twice
+    with the row and column transforms of every pass, against NumPy's FP64
+    FFT in the oracle.  Loss keeps M off unit modulus."""
+    wl = workloads.c2_plain_c64().with_(nx=n, ny=n, nz=2, d_eff=0.0, beta_f=0.0, beta_sh=0.0,
+                                        lx=2e-4 * n / 64, ly=2e-4 * n / 64, lcr=2e-3)
+    rng = np.random.Generator(np.random.PCG64(n))
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    a0 = ((rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))) * 1e6).astype(npdt)
+    b0 = ((rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))) * 3e5).astype(npdt)
+    plan = make_plan(wl, dtype)
+    gpu = run_gpu(plan, a0, b0)
+    ref = run_oracle(wl, a0, b0)
+    tol = 2e-6 if dtype == "c64" else 1e-13
+    assert rel(gpu[0], ref["a_f"]) < tol and rel(gpu[1], ref["a_sh"]) < tol
+    # diffraction acted: the output differs from the input well beyond rounding
+    assert rel(ref["a_sh"], b0.astype(complex)) > 1e-2
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_pointwise_nonlinear_step_on_random_states(dtype):
+    """The nonlinear step alone on random states: a 1 m window makes the
+    propagator the identity to ~1e-6 rad, so every cell runs the RK4 of its
+    own state (coupling, two-photon absorption, a per-step mismatch profile),
+    against the oracle's RK4."""
+    n = 64
+    wl = workloads.c2_plain_c64().with_(nx=n, ny=n, nz=30, lx=1.0, ly=1.0, alpha_f=0.0,
+                                        alpha_sh=0.0, beta_f=1e-10, beta_sh=2e-10)
+    rng = np.random.Generator(np.random.PCG64(5))
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    scale = 3e6
+    a0 = ((rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))) * scale).astype(npdt)
+    b0 = ((rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))) * 0.3 * scale).astype(npdt)
+    dk = wl.dk0 + 2000.0 * rng.normal(size=wl.nz)
+    plan = make_plan(wl, dtype)
+    gpu = run_gpu(plan, a0, b0, dk_z=dk)
+    ref = run_oracle(wl, a0, b0, dk_z=dk)
+    tol = 1e-5 if dtype == "c64" else 1e-12
+    assert rel(gpu[0], ref["a_f"]) < tol and rel(gpu[1], ref["a_sh"]) < tol
+    # the nonlinearity acted on every cell
+    lin = run_oracle(wl.with_(d_eff=0.0, beta_f=0.0, beta_sh=0.0), a0, b0, dk_z=dk)
+    assert rel(ref["a_sh"], lin["a_sh"]) > 1e-2
