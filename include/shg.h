@@ -144,7 +144,7 @@ size_t shg_workspace_bytes(const shg_plan *plan, int for_adjoint);
  *              dA, Sec. 2.2), or NULL
  *   stream     hipStream_t as void*
  * Errors: SHG_ESTATE, SHG_EINVAL (NULL field, 0 <= s_begin < s_end <= nz
- * violated), SHG_ENOMEM, SHG_EDEVICE. */
+ * violated), SHG_ENOMEM, SHG_EDEVICE, SHG_ENONFINITE (SHG_CHECK_FINITE). */
 int shg_propagate(shg_plan *plan, void *a_f, void *a_sh, const double *dk_z,
                   const void *temp, int32_t s_begin, int32_t s_end,
                   void *workspace, double *powers, void *stream);
@@ -161,7 +161,8 @@ int shg_propagate_heat(shg_plan *plan, void *a_f, void *a_sh, const double *dk_z
                        const void *temp, void *heat, void *workspace, double *powers,
                        void *stream);
 
-/* Gradient of a real loss L through the whole march (steps [0, nz)).
+/* Gradient of a real loss L through the whole march (steps [0, nz)), by the
+ * reverse of the Eq. 14 step sequence in the plan's split order.
  * The loss is L = Re<g_f_out, A_F(L)> + Re<g_sh_out, A_SH(L)>
  *               + w[0] P_F(L) + w[1] P_SH(L)  (to first order),
  * with complex gradients in the convention g = dL/dRe + i dL/dIm.
