@@ -55,7 +55,9 @@ extern "C" {
 
 typedef struct shg_plan shg_plan;
 
-typedef enum { SHG_C64 = 0, SHG_C128 = 1 } shg_dtype;
+/* (the last enumerator widens the type's range to every int32 value, so an
+ * invalid value passed by a caller is rejected, not undefined) */
+typedef enum { SHG_C64 = 0, SHG_C128 = 1, SHG_DTYPE_RANGE_ = 0x7fffffff } shg_dtype;
 
 enum {
   SHG_OK = 0,
