@@ -160,9 +160,16 @@ __device__ __forceinline__ int node_cls(const ThermGeom& g, int x, int y, int z)
 // 2.5-D tiling: a block of TX x TY threads owns an x-y tile and marches through
 // kThermZ planes.  The direction of the planes below and above stays in
 // registers; x and y neighbours come from an LDS copy of the current plane with
-// a one-node halo.  r and p_old are read about once per node (plus the halo).
+// a one-node halo.  Two copies alternate, so one barrier per plane suffices: a
+// copy is rewritten two planes later, after every thread has passed the barrier
+// of the plane in between.  The raw r and p_old of a thread's node (and of its
+// halo node, for threads on a tile edge) are loaded kThermPf planes ahead of
+// their use, so that several planes' loads are in flight per wavefront.  r and
+// p_old are read about once per node (plus the halo).  A node's class changes
+// along z only through its z role, so the per-class values are taken once.
 // p_new vanishes on oven nodes because r and p_old do and 1/diag is 0 there.
 constexpr int kThermZ = 16;
+constexpr int kThermPf = 4;
 
 template <typename R>
 __global__ void __launch_bounds__(256) th_direction_apply(ThermGeom g, const R* __restrict__ r,
@@ -170,54 +177,121 @@ __global__ void __launch_bounds__(256) th_direction_apply(ThermGeom g, const R* 
                                                           R* __restrict__ p_new, R* __restrict__ ap,
                                                           const double* __restrict__ sc,
                                                           double* __restrict__ part) {
-  __shared__ R tile[420];        // (TY + 2) x (TX + 2) <= 420 for TX TY = 256, TX in [16, 64]
+  __shared__ R tile[2][420];     // (TY + 2) x (TX + 2) <= 420 for TX TY = 256, TX in [16, 64]
   __shared__ double red[4];
   const int TX = blockDim.x, TY = blockDim.y;
   const int LW = TX + 2;
   const int tx = threadIdx.x, ty = threadIdx.y;
-  const int x = blockIdx.x * TX + tx, y = blockIdx.y * TY + ty;
-  const int z0 = blockIdx.z * kThermZ, z1 = min(z0 + kThermZ, g.nzn);
+  // Blocks are dealt to the 8 XCDs round-robin (dispatch index mod 8).  Tile
+  // lin = (b mod 8) (nb / 8) + b / 8 gives each XCD a contiguous run of tiles,
+  // x fastest, then y, then z, so the tiles whose halo rows a block reads run
+  // on the same XCD and share its L2.
+  const int nb = gridDim.x * gridDim.y * gridDim.z;
+  const int b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const int lin = nb % 8 == 0 ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int tile_x = lin % gridDim.x, tile_y = (lin / gridDim.x) % gridDim.y;
+  const int tile_z = lin / (gridDim.x * gridDim.y);
+  const int x = tile_x * TX + tx, y = tile_y * TY + ty;
+  const int z0 = tile_z * kThermZ, z1 = min(z0 + kThermZ, g.nzn);
   const size_t plane = (size_t)g.nx * g.ny;
   const R beta = (R)sc[kBeta];
-  auto pdir = [&](int xx, int yy, int zz) -> R {
-    const size_t j = (size_t)zz * plane + (size_t)yy * g.nx + xx;
-    return r[j] * (R)g.inv_diag[node_cls(g, xx, yy, zz)] + beta * p_old[j];
+  // halo node of a thread on a tile edge (TX, TY >= 4, so at most one x edge
+  // and one y edge): its column index, whether it lies inside the grid, and
+  // its LDS slot; a thread off the edges has no halo node (slot -1)
+  const int hx = tx == 0 ? x - 1 : x + 1;
+  const int sx = tx == 0 ? (ty + 1) * LW : (tx == TX - 1 ? (ty + 1) * LW + TX + 1 : -1);
+  const bool inx = sx >= 0 && hx >= 0 && hx < g.nx;
+  const int hy = ty == 0 ? y - 1 : y + 1;
+  const int sy = ty == 0 ? tx + 1 : (ty == TY - 1 ? (TY + 1) * LW + tx + 1 : -1);
+  const bool iny = sy >= 0 && hy >= 0 && hy < g.ny;
+  // per z role (0 interior, 1 first plane, 2 last plane): 1 / diag of the node
+  // and of its halo nodes, and w and the oven flag of the node
+  const int bc = role(x, g.nx) + 3 * role(y, g.ny);
+  const int bx = inx ? role(hx, g.nx) + 3 * role(y, g.ny) : 0;
+  const int by = iny ? role(x, g.nx) + 3 * role(hy, g.ny) : 0;
+  R dc[3], dx[3], dy[3], wc[3];
+  int oc[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    dc[k] = (R)g.inv_diag[bc + 9 * k];
+    dx[k] = (R)g.inv_diag[bx + 9 * k];
+    dy[k] = (R)g.inv_diag[by + 9 * k];
+    wc[k] = (R)g.w[bc + 9 * k];
+    oc[k] = g.oven[bc + 9 * k];
+  }
+  const size_t col = (size_t)y * g.nx + x;
+  const size_t colx = (size_t)y * g.nx + hx, coly = (size_t)hy * g.nx + x;
+  // raw values: node of plane z0 - 1 + j (j = 0 .. kThermZ + 1), halo nodes of
+  // plane z0 + j (j = 0 .. kThermZ - 1); zero outside the grid
+  R cr[kThermZ + 2], cp[kThermZ + 2], xr[kThermZ], xp[kThermZ], yr[kThermZ], yp[kThermZ];
+  auto load_c = [&](int j) {
+    const int zz = z0 - 1 + j;
+    cr[j] = (R)0;
+    cp[j] = (R)0;
+    if (zz >= 0 && zz < g.nzn) {
+      const size_t i = (size_t)zz * plane + col;
+      cr[j] = r[i];
+      cp[j] = p_old[i];
+    }
   };
+  auto load_h = [&](int j) {
+    const int zz = z0 + j;
+    xr[j] = xp[j] = yr[j] = yp[j] = (R)0;
+    if (zz < g.nzn) {
+      if (inx) {
+        const size_t i = (size_t)zz * plane + colx;
+        xr[j] = r[i];
+        xp[j] = p_old[i];
+      }
+      if (iny) {
+        const size_t i = (size_t)zz * plane + coly;
+        yr[j] = r[i];
+        yp[j] = p_old[i];
+      }
+    }
+  };
+  auto zrole = [&](int zz) { return zz == 0 ? 1 : (zz == g.nzn - 1 ? 2 : 0); };
+#pragma unroll
+  for (int j = 0; j < kThermPf + 2; ++j) load_c(j);
+#pragma unroll
+  for (int j = 0; j < kThermPf; ++j) load_h(j);
   const R ih2x = (R)g.ih2[0], ih2y = (R)g.ih2[1], ih2z = (R)g.ih2[2];
-  R pm = z0 > 0 ? pdir(x, y, z0 - 1) : (R)0;
-  R pc = pdir(x, y, z0);
+  R pm = cr[0] * dc[z0 > 0 ? zrole(z0 - 1) : 0] + beta * cp[0];
+  R pc = cr[1] * dc[zrole(z0)] + beta * cp[1];
   double pap = 0.0;
-  for (int z = z0; z < z1; ++z) {
-    const R pn = z + 1 < g.nzn ? pdir(x, y, z + 1) : (R)0;
-    // plane z into LDS with its x / y halo (outside the grid: unused)
-    tile[(ty + 1) * LW + tx + 1] = pc;
-    if (tx == 0) tile[(ty + 1) * LW] = x > 0 ? pdir(x - 1, y, z) : (R)0;
-    if (tx == TX - 1) tile[(ty + 1) * LW + TX + 1] = x + 1 < g.nx ? pdir(x + 1, y, z) : (R)0;
-    if (ty == 0) tile[tx + 1] = y > 0 ? pdir(x, y - 1, z) : (R)0;
-    if (ty == TY - 1) tile[(TY + 1) * LW + tx + 1] = y + 1 < g.ny ? pdir(x, y + 1, z) : (R)0;
+#pragma unroll
+  for (int k = 0; k < kThermZ; ++k) {
+    const int z = z0 + k;
+    if (z >= z1) break;
+    if (k + kThermPf + 2 < kThermZ + 2) load_c(k + kThermPf + 2);
+    if (k + kThermPf < kThermZ) load_h(k + kThermPf);
+    const int zr = zrole(z);
+    const R pn = cr[k + 2] * dc[z + 1 < g.nzn ? zrole(z + 1) : 0] + beta * cp[k + 2];
+    R* t = tile[k & 1];
+    t[(ty + 1) * LW + tx + 1] = pc;
+    if (sx >= 0) t[sx] = xr[k] * dx[zr] + beta * xp[k];
+    if (sy >= 0) t[sy] = yr[k] * dy[zr] + beta * yp[k];
     __syncthreads();
-    const int cls = node_cls(g, x, y, z);
-    const size_t i = (size_t)z * plane + (size_t)y * g.nx + x;
+    const size_t i = (size_t)z * plane + col;
     R a = (R)0;
-    if (!g.oven[cls]) {
-      const R xm = tile[(ty + 1) * LW + tx], xp = tile[(ty + 1) * LW + tx + 2];
-      const R ym = tile[ty * LW + tx + 1], yp = tile[(ty + 2) * LW + tx + 1];
+    if (!oc[zr]) {
+      const R xm = t[(ty + 1) * LW + tx], xq = t[(ty + 1) * LW + tx + 2];
+      const R ym = t[ty * LW + tx + 1], yq = t[(ty + 2) * LW + tx + 1];
       R acc;
-      if (x == 0) acc = (pc - xp) * ((R)2 * ih2x) + (R)g.conv_lo[0] * pc;
+      if (x == 0) acc = (pc - xq) * ((R)2 * ih2x) + (R)g.conv_lo[0] * pc;
       else if (x == g.nx - 1) acc = (pc - xm) * ((R)2 * ih2x) + (R)g.conv_hi[0] * pc;
-      else acc = ((R)2 * pc - xp - xm) * ih2x;
-      if (y == 0) acc += (pc - yp) * ((R)2 * ih2y) + (R)g.conv_lo[1] * pc;
+      else acc = ((R)2 * pc - xq - xm) * ih2x;
+      if (y == 0) acc += (pc - yq) * ((R)2 * ih2y) + (R)g.conv_lo[1] * pc;
       else if (y == g.ny - 1) acc += (pc - ym) * ((R)2 * ih2y) + (R)g.conv_hi[1] * pc;
-      else acc += ((R)2 * pc - yp - ym) * ih2y;
+      else acc += ((R)2 * pc - yq - ym) * ih2y;
       if (z == 0) acc += (pc - pn) * ((R)2 * ih2z) + (R)g.conv_lo[2] * pc;
       else if (z == g.nzn - 1) acc += (pc - pm) * ((R)2 * ih2z) + (R)g.conv_hi[2] * pc;
       else acc += ((R)2 * pc - pn - pm) * ih2z;
-      a = (R)g.w[cls] * acc;
+      a = wc[zr] * acc;
       pap += (double)pc * (double)a;
     }
     p_new[i] = pc;
     ap[i] = a;
-    __syncthreads();   // the tile is rewritten for the next plane
     pm = pc;
     pc = pn;
   }
@@ -227,10 +301,7 @@ __global__ void __launch_bounds__(256) th_direction_apply(ThermGeom g, const R* 
   for (int off = 32; off > 0; off >>= 1) pap += __shfl_down(pap, off, 64);
   if ((flat & 63) == 0) red[flat >> 6] = pap;
   __syncthreads();
-  if (flat == 0) {
-    const size_t b = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    part[b] = red[0] + red[1] + red[2] + red[3];
-  }
+  if (flat == 0) part[lin] = red[0] + red[1] + red[2] + red[3];
 }
 
 // theta += alpha p; r -= alpha Ap; partials of r.z and r.r.
@@ -268,9 +339,24 @@ __global__ void __launch_bounds__(256) th_scalars(const double* __restrict__ par
   __shared__ double red[4];
   double a = 0.0, b = 0.0;
   const int stride = (mode == 1) ? 1 : 2;
-  for (int k = threadIdx.x; k < nblk; k += 256) {
-    a += part[stride * k];
-    if (stride == 2) b += part[stride * k + 1];
+  // each thread sums its partials k = tid, tid + 256, ... in that order; the
+  // loads of eight of them are issued before the first is added
+  constexpr int U = 8;
+  for (int k0 = threadIdx.x; k0 < nblk; k0 += 256 * U) {
+    double va[U], vb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + 256 * u;
+      va[u] = k < nblk ? part[stride * k] : 0.0;
+      vb[u] = (stride == 2 && k < nblk) ? part[stride * k + 1] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (k0 + 256 * u < nblk) {
+        a += va[u];
+        b += vb[u];
+      }
+    }
   }
   a = block_sum256(a, red);
   b = block_sum256(b, red);
