@@ -310,8 +310,45 @@ struct TwRegs {
   Tw<R> w[count > 0 ? count : 1];
 };
 
+// Global-memory view of a device pointer.  Pointers that kernels read from a
+// table in memory (the instances of a batch) are generic to the compiler,
+// which then issues flat memory instructions; those count against the LDS
+// counter as well, so every LDS wait of a transform would also wait for the
+// loads issued ahead of it.  An explicit conversion to the global address
+// space gives global instructions (a no-op for pointers that are kernel
+// arguments, which the compiler already knows to be global).
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+
+template <typename T>
+__device__ __forceinline__ gmem<T>* gp(T* q) {
+  return (gmem<T>*)q;
+}
+
+// Loads and stores of the complex and twiddle types through a global view:
+// class types cannot be assigned to or from address-space-qualified objects,
+// so they move as builtin vectors of 32-bit words.
+template <typename T>
+__device__ __forceinline__ T gload(const gmem<T>* q) {
+  static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
+  typedef unsigned V __attribute__((ext_vector_type(sizeof(T) / 4), aligned(alignof(T))));
+  return __builtin_bit_cast(T, *reinterpret_cast<const gmem<V>*>(q));
+}
+
+template <typename T>
+__device__ __forceinline__ T gload(const T* q) {
+  return *q;
+}
+
+template <typename T>
+__device__ __forceinline__ void gstore(gmem<T>* q, T x) {
+  static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
+  typedef unsigned V __attribute__((ext_vector_type(sizeof(T) / 4), aligned(alignof(T))));
+  *reinterpret_cast<gmem<V>*>(q) = __builtin_bit_cast(V, x);
+}
+
 template <typename R, int N, int G, int NS, int REM>
-__device__ __forceinline__ void tw_gather(Tw<R>* out, int t, const Tw<R>* __restrict__ tw) {
+__device__ __forceinline__ void tw_gather(Tw<R>* out, int t, const gmem<Tw<R>>* __restrict__ tw) {
   if constexpr (REM > 1) {
     constexpr int E = N / G;
     constexpr int RP = pick_radix<E, REM>::value;
@@ -321,7 +358,7 @@ __device__ __forceinline__ void tw_gather(Tw<R>* out, int t, const Tw<R>* __rest
       for (int u = 0; u < NB; ++u) {
         const int jm = (t + G * u) % NS;
 #pragma unroll
-        for (int r = 1; r < RP; ++r) out[u * (RP - 1) + (r - 1)] = tw[jm * r * (N / (NS * RP))];
+        for (int r = 1; r < RP; ++r) out[u * (RP - 1) + (r - 1)] = gload(tw + jm * r * (N / (NS * RP)));
       }
       tw_gather<R, N, G, NS * RP, REM / RP>(out + NB * (RP - 1), t, tw);
     } else {
@@ -332,7 +369,7 @@ __device__ __forceinline__ void tw_gather(Tw<R>* out, int t, const Tw<R>* __rest
 
 template <typename R, int N, int G>
 __device__ __forceinline__ void tw_load(TwRegs<R, N, G>& T, int t, const Tw<R>* __restrict__ tw) {
-  tw_gather<R, N, G, 1, N>(T.w, t, tw);
+  tw_gather<R, N, G, 1, N>(T.w, t, gp(tw));
 }
 
 // Barrier between Stockham passes.  WAVE: every transform belongs to the

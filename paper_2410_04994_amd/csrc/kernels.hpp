@@ -44,13 +44,13 @@ struct HalfStep {
 // e = exp(-i phi): cf = i kappa_F e, cs = i kappa_SH conj(e).  The stage
 // points are e[0], e[stride], e[2 stride] of the step's 5-point table: stride 1
 // for a half-step, 2 for a full step (L/2 - N - L/2 order).
-template <typename R>
-__device__ __forceinline__ HalfStep<R> half_step_coefs(const cx<R>* __restrict__ e, R kf, R ks,
+template <typename R, typename P>
+__device__ __forceinline__ HalfStep<R> half_step_coefs(P __restrict__ e, R kf, R ks,
                                                        int stride = 1) {
   HalfStep<R> h;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const cx<R> ek = e[k * stride];
+    const cx<R> ek = gload(e + k * stride);
     h.cf[k] = {-kf * ek.im, kf * ek.re};
     h.cs[k] = {ks * ek.im, ks * ek.re};
   }
@@ -269,11 +269,13 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
   const int rr = threadIdx.x / G;
   const int y = blk * ROWS + rr;
   const size_t row = (size_t)y * N;
+  const auto ain = gp(p.ain), bin = gp(p.bin);
+  const auto aout = gp(p.aout), bout = gp(p.bout);
   cx<R> va[E], vb[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
-    va[m] = p.ain[row + t + G * m];
-    vb[m] = p.bin[row + t + G * m];
+    va[m] = gload(ain + (row + t + G * m));
+    vb[m] = gload(bin + (row + t + G * m));
   }
   const LdsView<R, 1> a0{&lds[rr][0][0][0]}, a1{&lds[rr][0][1][0]};
   const LdsView<R, 1> b0{&lds[rr][1][0][0]}, b1{&lds[rr][1][1][0]};
@@ -284,8 +286,8 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
   const int stf = p.full ? 2 : 1;
   HalfStep<R> c2{}, c1{};
   if constexpr (!TH) {
-    if (p.s_second >= 0) c2 = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);
-    if (p.s_first >= 0) c1 = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, stf);
+    if (p.s_second >= 0) c2 = half_step_coefs(gp(p.phase) + 5 * p.s_second + 2, p.kf, p.ks);
+    if (p.s_first >= 0) c1 = half_step_coefs(gp(p.phase) + 5 * p.s_first, p.kf, p.ks, stf);
   }
   if (p.inv_in) {
     fft_pre<R, N, G, true, 1, (G <= 64)>(va, a0, a1, t, twr);
@@ -293,10 +295,11 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
   }
   const bool und = p.undepleted != 0;
   if (p.tap_a) {
+    const auto ta = gp(p.tap_a), tb = gp(p.tap_b);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      p.tap_a[row + t + G * m] = va[m];
-      p.tap_b[row + t + G * m] = vb[m];
+      gstore(ta + (row + t + G * m), va[m]);
+      gstore(tb + (row + t + G * m), vb[m]);
     }
   }
   if constexpr (TH) {
@@ -336,8 +339,9 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
       for (int m = 0; m < E; ++m) rk4_cell(va[m], vb[m], c2, p.tf, p.ts, p.h, und);
     }
     if (p.heat) {
+      const auto ht = gp(p.heat);
 #pragma unroll
-      for (int m = 0; m < E; ++m) p.heat[row + t + G * m] = heat_density(va[m], vb[m], p);
+      for (int m = 0; m < E; ++m) ht[row + t + G * m] = heat_density(va[m], vb[m], p);
     }
     if (p.s_first >= 0) {
 #pragma unroll
@@ -350,8 +354,8 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
   }
 #pragma unroll
   for (int m = 0; m < E; ++m) {
-    p.aout[row + t + G * m] = va[m];
-    p.bout[row + t + G * m] = vb[m];
+    gstore(aout + (row + t + G * m), va[m]);
+    gstore(bout + (row + t + G * m), vb[m]);
   }
   if (p.partials) {
     double sa = 0.0, sb = 0.0;
@@ -362,8 +366,9 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
     }
     block_sum2<G * ROWS>(sa, sb, red);
     if (threadIdx.x == 0) {
-      p.partials[2 * blk] = sa;
-      p.partials[2 * blk + 1] = sb;
+      const auto pt = gp(p.partials);
+      pt[2 * blk] = sa;
+      pt[2 * blk + 1] = sb;
     }
   }
 }
@@ -471,14 +476,14 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
       if (p.full) psi2 += dkc * p.dz;
     }
   } else {
-    if (p.s_second >= 0) c2 = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);
-    if (p.s_first >= 0) c1 = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, stf);
+    if (p.s_second >= 0) c2 = half_step_coefs(gp(p.phase) + 5 * p.s_second + 2, p.kf, p.ks);
+    if (p.s_first >= 0) c1 = half_step_coefs(gp(p.phase) + 5 * p.s_first, p.kf, p.ks, stf);
   }
   if (p.inv_in) {
     if (fth) {
-      const cx<R>* src = ff ? p.bin : p.ain;
+      const auto src = gp(ff ? p.bin : p.ain);
 #pragma unroll
-      for (int m = 0; m < EF; ++m) v[m] = src[frow + t + G * m];
+      for (int m = 0; m < EF; ++m) v[m] = gload(src + (frow + t + G * m));
     }
     fft_pre<R, N, G, true, 1, (G <= 64)>(v, q0, q1, t, twr, fth);
     if (fth) {
@@ -489,12 +494,12 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
     a = cell[0][cr][pad16(cxi)];
     b = cell[1][cr][pad16(cxi)];
   } else {
-    a = p.ain[idx];
-    b = p.bin[idx];
+    a = gload(gp(p.ain) + idx);
+    b = gload(gp(p.bin) + idx);
   }
   if (p.tap_a) {
-    p.tap_a[idx] = a;
-    p.tap_b[idx] = b;
+    gstore(gp(p.tap_a) + idx, a);
+    gstore(gp(p.tap_b) + idx, b);
   }
   const bool und = p.undepleted != 0;
   if constexpr (TH) {
@@ -505,7 +510,7 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
     if (p.s_second >= 0 || (p.full && p.s_first >= 0)) p.psi[idx] = psi2;
   } else {
     if (p.s_second >= 0) rk4_cell(a, b, c2, p.tf, p.ts, p.h, und);
-    if (p.heat) p.heat[idx] = heat_density(a, b, p);
+    if (p.heat) gp(p.heat)[idx] = heat_density(a, b, p);
     if (p.s_first >= 0) rk4_cell(a, b, c1, p.tf, p.ts, p.h * stf, und);
   }
   if (p.fwd_out) {
@@ -520,21 +525,22 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
     }
     fft_pre<R, N, G, false, 1, (G <= 64)>(v, q0, q1, t, twr, fth);
     if (fth) {
-      cx<R>* dst = ff ? p.bout : p.aout;
+      const auto dst = gp(ff ? p.bout : p.aout);
 #pragma unroll
-      for (int m = 0; m < EF; ++m) dst[frow + t + G * m] = v[m];
+      for (int m = 0; m < EF; ++m) gstore(dst + (frow + t + G * m), v[m]);
     }
   } else {
-    p.aout[idx] = a;
-    p.bout[idx] = b;
+    gstore(gp(p.aout) + idx, a);
+    gstore(gp(p.bout) + idx, b);
   }
   if (p.partials) {
     double sa = (double)a.re * (double)a.re + (double)a.im * (double)a.im;
     double sb = (double)b.re * (double)b.re + (double)b.im * (double)b.im;
     block_sum2<S::threads>(sa, sb, red);
     if (threadIdx.x == 0) {
-      p.partials[2 * blk] = sa;
-      p.partials[2 * blk + 1] = sb;
+      const auto pt = gp(p.partials);
+      pt[2 * blk] = sa;
+      pt[2 * blk + 1] = sb;
     }
   }
 }
@@ -578,14 +584,18 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& p) {
   const int field = lin / p.tiles;
   const int tile = lin - field * p.tiles;
   const int x = tile * TC + c;
-  cx<R>* __restrict__ col = p.f[field] + x;
+  // the field pointer is uniform per block; element offsets fit in 32 bits
+  // (a field holds at most 512 x 512 elements)
+  const auto fld = gp(p.f[field]);
+  const unsigned o0 = (unsigned)x + (unsigned)t * (unsigned)p.nx;
+  const unsigned og = (unsigned)(G * p.nx);
   cx<R> v[E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) v[m] = col[(size_t)(t + G * m) * p.nx];
+  for (int m = 0; m < E; ++m) v[m] = gload(fld + (o0 + (unsigned)m * og));
   // diffraction + linear loss (Eq. A.4): the FP64 product m_x m_y of this
   // thread's bins, formed before the transforms so that its loads overlap FFT_y
-  const double* __restrict__ mxp = p.mx[field];
-  const double* __restrict__ myp = p.my[field];
+  const auto mxp = gp(p.mx[field]);
+  const auto myp = gp(p.my[field]);
   const double sgn = p.conj_prop ? -1.0 : 1.0;
   const double mxr = mxp[2 * x], mxi = sgn * mxp[2 * x + 1];
   double mr[E], mi[E];
@@ -607,7 +617,7 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& p) {
   }
   fft_pre<R, N, G, true, TC, WAVE>(v, b0, b1, t, twr);
 #pragma unroll
-  for (int m = 0; m < E; ++m) col[(size_t)(t + G * m) * p.nx] = v[m];
+  for (int m = 0; m < E; ++m) gstore(fld + (o0 + (unsigned)m * og), v[m]);
 }
 
 template <typename R, int N, int G, int TC>
