@@ -506,9 +506,9 @@ __global__ void __launch_bounds__(WideShape<N>::threads) row_adj_pass_wide(RowAd
   const AdjPre<R, TH> pre = adj_load<R, TH>(p, q, idx, n2);
   if (p.inv_in) {
     if (fth) {
-      const cx<R>* src = ff ? p.lb : p.la;
+      const auto src = gp(ff ? p.lb : p.la);
 #pragma unroll
-      for (int m = 0; m < EF; ++m) v[m] = src[frow + t + G * m];
+      for (int m = 0; m < EF; ++m) v[m] = gload(src + (frow + t + G * m));
     }
     fft_pre<R, N, G, true, 1, (G <= 64)>(v, q0, q1, t, twr, fth);
     if (fth) {
@@ -519,8 +519,8 @@ __global__ void __launch_bounds__(WideShape<N>::threads) row_adj_pass_wide(RowAd
     la = cell[0][cr][pad16(cxi)];
     lb = cell[1][cr][pad16(cxi)];
   } else {
-    la = p.la[idx];
-    lb = p.lb[idx];
+    la = gload(gp(p.la) + idx);
+    lb = gload(gp(p.lb) + idx);
   }
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   adj_cell<R, TH>(p, q, pre, idx, la, lb, acc);
@@ -535,9 +535,9 @@ __global__ void __launch_bounds__(WideShape<N>::threads) row_adj_pass_wide(RowAd
     }
     fft_pre<R, N, G, false, 1, (G <= 64)>(v, q0, q1, t, twr, fth);
     if (fth) {
-      cx<R>* dst = ff ? p.lb : p.la;
+      const auto dst = gp(ff ? p.lb : p.la);
 #pragma unroll
-      for (int m = 0; m < EF; ++m) dst[frow + t + G * m] = v[m];
+      for (int m = 0; m < EF; ++m) gstore(dst + (frow + t + G * m), v[m]);
     }
   } else {
     p.la[idx] = la;

@@ -633,11 +633,13 @@ template <typename R>
 __device__ __forceinline__ void phase_table_body(const double* __restrict__ dk_z, double dk0,
                                                  int nz, double dz, cx<R>* __restrict__ out) {
   __shared__ double part[256];
+  const auto dkg = gp(dk_z);
+  const auto og = gp(out);
   const int tid = threadIdx.x;
   const int chunk = (nz + 255) / 256;
   const int s0 = min(nz, tid * chunk), s1 = min(nz, s0 + chunk);
   double sum = 0.0;
-  for (int s = s0; s < s1; ++s) sum += (dk_z ? dk_z[s] : dk0) * dz;
+  for (int s = s0; s < s1; ++s) sum += (dk_z ? dkg[s] : dk0) * dz;
   part[tid] = sum;
   __syncthreads();
   if (tid == 0) {
@@ -651,12 +653,12 @@ __device__ __forceinline__ void phase_table_body(const double* __restrict__ dk_z
   __syncthreads();
   double phi = part[tid];
   for (int s = s0; s < s1; ++s) {
-    const double dk = dk_z ? dk_z[s] : dk0;
+    const double dk = dk_z ? dkg[s] : dk0;
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       double sn, cs;
       sincos(phi + dk * (0.25 * k * dz), &sn, &cs);
-      out[5 * s + k] = {(R)cs, (R)(-sn)};
+      gstore(og + (5 * s + k), cx<R>{(R)cs, (R)(-sn)});
     }
     phi += dk * dz;
   }
@@ -784,15 +786,17 @@ __global__ void __launch_bounds__(256) power_finalize_batch(const BatchInst<R>* 
   __shared__ double red[8];
   const BatchInst<R>& I = inst[blockIdx.x];
   if (!I.powers) return;
+  const auto part = gp(I.partials);
   double x = 0.0, y = 0.0;
   for (int i = threadIdx.x; i < I.row_blocks; i += 256) {
-    x += I.partials[2 * i];
-    y += I.partials[2 * i + 1];
+    x += part[2 * i];
+    y += part[2 * i + 1];
   }
   block_sum2<256>(x, y, red);
   if (threadIdx.x == 0) {
-    I.powers[0] = x * I.pscale_f;
-    I.powers[1] = y * I.pscale_sh;
+    const auto pw = gp(I.powers);
+    pw[0] = x * I.pscale_f;
+    pw[1] = y * I.pscale_sh;
   }
 }
 
