@@ -89,6 +89,9 @@ def main(argv=None):
     ap.add_argument("--cpu-sample-steps", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="",
+                    help="comma-separated extra lines to run (default: all of "
+                         "batched, fwd_adj, thermal_fwd_adj, lnl, thermal, self_consistent)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 64 MiB device copy from a cache-cold source "
                          "(reference for the HBM byte counters)")
@@ -184,7 +187,8 @@ def main(argv=None):
     if not args.no_extras:
         try:
             from paper_2410_04994_amd import extras
-            out["extras"] = extras.run_all(dev)
+            only = [x for x in args.extras.split(",") if x] or None
+            out["extras"] = extras.run_all(dev, only)
         except Exception as exc:  # extras must never hide the main line
             out["extras"] = {"error": f"{type(exc).__name__}: {exc}"}
     if not args.no_cpu_baseline:

@@ -280,10 +280,18 @@ def lnl(device, steps=5):
     return out
 
 
-def run_all(device) -> dict:
+def run_all(device, only=None) -> dict:
+    """Every extra line, or those named in `only`."""
+    lines = (("batched", batched), ("fwd_adj", fwd_adj), ("thermal_fwd_adj", thermal_fwd_adj),
+             ("lnl", lnl), ("thermal", thermal), ("self_consistent", self_consistent_loop))
+    known = [name for name, _ in lines]
+    unknown = [x for x in (only or []) if x not in known]
+    if unknown:
+        raise ValueError(f"unknown extra lines {unknown}; known: {known}")
     out = {}
-    for name, fn in (("batched", batched), ("fwd_adj", fwd_adj), ("thermal_fwd_adj", thermal_fwd_adj),
-                     ("lnl", lnl), ("thermal", thermal), ("self_consistent", self_consistent_loop)):
+    for name, fn in lines:
+        if only is not None and name not in only:
+            continue
         try:
             out[name] = fn(device)
         except Exception as exc:

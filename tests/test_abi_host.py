@@ -218,3 +218,9 @@ def test_unknown_thermal_method_rejected(lib):
     h = ctypes.c_void_p()
     assert lib.shg_thermal_create(ctypes.byref(h), ctypes.byref(tp), 0) == binding.SHG_EINVAL
     assert "method" in lib.shg_last_error().decode()
+
+
+def test_bench_extras_selection_rejects_unknown_lines():
+    from paper_2410_04994_amd import extras
+    with pytest.raises(ValueError, match="unknown extra lines"):
+        extras.run_all(None, ["batched", "no_such_line"])
