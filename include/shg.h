@@ -267,11 +267,12 @@ typedef struct shg_thermal shg_thermal;
 
 enum { SHG_FACE_AIR = 0, SHG_FACE_OVEN = 1, SHG_FACE_INSULATED = 2 };
 
-/* Solvers.  SHG_THERMAL_DIRECT: fast diagonalisation.  Divided by the
- * control-volume weights, the operator is the Kronecker sum of three 1-D
- * operators (constant k, oven faces are whole planes), so T follows exactly
- * from their eigendecompositions (rocSOLVER, once per plan, FP64) and six FP64
- * GEMM mode products (rocBLAS) per solve; tol and max_iter are ignored and
+/* Solvers.  SHG_THERMAL_DIRECT: exact.  Divided by the control-volume
+ * weights, the operator is the Kronecker sum of three 1-D operators (constant
+ * k, oven faces are whole planes).  The x and y operators are diagonalised
+ * (rocSOLVER eigendecompositions, once per plan, FP64; four FP64 GEMM mode
+ * products per solve), which leaves one tridiagonal system along z per (x, y)
+ * mode, solved by elimination in FP64; tol and max_iter are ignored and
  * iterations is 0.  SHG_THERMAL_CG: Jacobi-preconditioned conjugate gradients
  * in the plan's real type with FP64 reductions, stopped at |r| <= tol |b|. */
 enum { SHG_THERMAL_DIRECT = 0, SHG_THERMAL_CG = 1 };

@@ -372,7 +372,7 @@ THERMAL_METHODS = {"direct": 0, "cg": 1}
 def make_thermal_params(params: dict, k_th: float, h_conv: float, t_inf: float, t_oven: float,
                         faces: dict, method: str = "direct") -> ThermalParams:
     """faces: face name ("x-" .. "z+") -> "oven" | "air" | "insulated" (default air);
-    method: "direct" (fast diagonalisation) or "cg"."""
+    method: "direct" (exact: x-y diagonalisation, tridiagonal solves along z) or "cg"."""
     tp = ThermalParams()
     tp.nx, tp.ny, tp.nz = int(params["nx"]), int(params["ny"]), int(params["nz"])
     for i, f in enumerate(FACE_NAMES):

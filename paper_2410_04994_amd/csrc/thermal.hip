@@ -1,5 +1,6 @@
 // Heat equation and the self-consistent field <-> temperature loop: thermal
-// plans, the two solvers (fast diagonalisation with FP64 GEMMs, the default;
+// plans, the two solvers (diagonalisation in x and y with FP64 GEMMs and
+// tridiagonal solves along z, the default;
 // Jacobi-preconditioned conjugate gradients) and the loop of the flowchart in
 // Sec. 4 (q = 0 -> T -> march with dk(T) -> q -> T -> ...).
 #include <hip/hip_runtime.h>
@@ -25,6 +26,8 @@ struct Fdm {
   double* pm[3] = {};       // forward factors P_d (column-major m_d x m_d)
   double* qm[3] = {};       // backward factors Q_d
   double* lam[3] = {};      // eigenvalues
+  double* tz_diag = nullptr;   // z: diagonal and off-diagonal of A_z = W^-1 S (tridiagonal solve)
+  double* tz_off = nullptr;
 };
 
 struct Therm {
@@ -228,6 +231,9 @@ static void free_fdm(Fdm& f) {
     if (f.lam[d]) (void)hipFree(f.lam[d]);
     f.pm[d] = f.qm[d] = f.lam[d] = nullptr;
   }
+  if (f.tz_diag) (void)hipFree(f.tz_diag);
+  if (f.tz_off) (void)hipFree(f.tz_off);
+  f.tz_diag = f.tz_off = nullptr;
   if (f.h) (void)rocblas_destroy_handle(f.h);
   f.h = nullptr;
   f.ready = false;
@@ -237,8 +243,9 @@ static int blas_fail(rocblas_status s, const char* what) {
   return fail(SHG_EDEVICE, "%s: %s", what, rocblas_status_to_string(s));
 }
 
-// The 1-D operators, their eigendecompositions (rocSOLVER, tridiagonal divide
-// and conquer, FP64) and the factors P_d, Q_d.
+// The 1-D operators; for x and y their eigendecompositions (rocSOLVER,
+// tridiagonal divide and conquer, FP64) and the factors P_d, Q_d; for z the
+// tridiagonal A_z itself, solved per mode pair.
 static int fdm_setup(Therm& th, hipStream_t st) {
   Fdm& f = th.fdm;
   if (f.ready) return SHG_OK;
@@ -281,6 +288,20 @@ static int fdm_setup(Therm& th, hipStream_t st) {
       }
     }
     for (int k = 0; k < m; ++k) D[k] = sd[k] / w[k];
+    if (d == 2) {
+      // A_z = W^-1 S: diagonal sd/w, off-diagonal -ih2/w in each row
+      std::vector<double> od(m);
+      for (int k = 0; k < m; ++k) od[k] = -ih2 / w[k];
+      e = hipMalloc(&f.tz_diag, m * sizeof(double));
+      if (e == hipSuccess) e = hipMalloc(&f.tz_off, m * sizeof(double));
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(f.tz_diag, D.data(), m * sizeof(double), hipMemcpyHostToDevice, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(f.tz_off, od.data(), m * sizeof(double), hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) rc = hip_fail(e, "direct solver set-up");
+      continue;
+    }
     for (int k = 0; k + 1 < m; ++k) E[k] = -ih2 / std::sqrt(w[k] * w[k + 1]);
     const size_t mm = (size_t)m * m;
     e = hipMalloc(&dd, m * sizeof(double));
@@ -393,15 +414,13 @@ static int solve_direct(Therm& th, const R* heat, R* t_nodes, R* t_mid, char* ws
   const size_t np = (size_t)f.box.m[0] * f.box.m[1] * f.box.m[2];
   const dim3 grid((unsigned)std::min<size_t>(4096, (np + 255) / 256)), blk(256);
   hipLaunchKernelGGL((fdm_gather<R>), grid, blk, 0, st, g, f.box, heat, f0);
-  // forward transforms x, y, z; divide; backward transforms
-  if ((rc = fdm_mode(f, 0, f.pm[0], f0, f1)) || (rc = fdm_mode(f, 1, f.pm[1], f1, f0)) ||
-      (rc = fdm_mode(f, 2, f.pm[2], f0, f1)))
-    return rc;
-  hipLaunchKernelGGL(fdm_divide, grid, blk, 0, st, f.box, (const double*)f.lam[0],
-                     (const double*)f.lam[1], (const double*)f.lam[2], f1);
-  if ((rc = fdm_mode(f, 0, f.qm[0], f1, f0)) || (rc = fdm_mode(f, 1, f.qm[1], f0, f1)) ||
-      (rc = fdm_mode(f, 2, f.qm[2], f1, f0)))
-    return rc;
+  // forward transforms x, y; tridiagonal solves along z; backward transforms
+  if ((rc = fdm_mode(f, 0, f.pm[0], f0, f1)) || (rc = fdm_mode(f, 1, f.pm[1], f1, f0))) return rc;
+  const size_t nxy = (size_t)f.box.m[0] * f.box.m[1];
+  hipLaunchKernelGGL(fdm_tri_z, dim3((unsigned)std::min<size_t>(4096, (nxy + 255) / 256)), blk, 0, st,
+                     f.box, (const double*)f.lam[0], (const double*)f.lam[1],
+                     (const double*)f.tz_diag, (const double*)f.tz_off, f0, f1);
+  if ((rc = fdm_mode(f, 0, f.qm[0], f0, f1)) || (rc = fdm_mode(f, 1, f.qm[1], f1, f0))) return rc;
   // f1 <- theta in FP64 on all nodes (the packed solution in f0 is then free)
   hipLaunchKernelGGL((fdm_scatter<R>), dim3(th.nblk), blk, 0, st, g, f.box, (const double*)f0,
                      th.p.t_oven, f1, t_nodes);

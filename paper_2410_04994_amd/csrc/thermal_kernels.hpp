@@ -413,14 +413,15 @@ __global__ void __launch_bounds__(256) th_max_final(const double* __restrict__ p
 }
 
 // ---------------------------------------------------------------- direct solve
-// Fast diagonalisation: the operator divided by the control-volume weights is
-// the Kronecker sum L_x + L_y + L_z of 1-D operators on the free nodes (the
-// oven faces are whole planes), each L_d = W_d^-1 S_d with S_d symmetric
-// tridiagonal.  With W_d^-1/2 S_d W_d^-1/2 = U_d Lambda_d U_d^T:
-//   theta = (Q_z x Q_y x Q_x) [ (P_z x P_y x P_x) f / (lx + ly + lz) ],
-//   P_d = U_d^T W_d^1/2,  Q_d = W_d^-1/2 U_d,  f = b / w = q / k + boundary terms.
-// The mode products are FP64 GEMMs; these kernels gather f, divide by the
-// eigenvalue sums and scatter theta back.
+// The operator divided by the control-volume weights is the Kronecker sum
+// L_x + L_y + L_z of 1-D operators on the free nodes (the oven faces are whole
+// planes), each L_d = W_d^-1 S_d with S_d symmetric tridiagonal.  With
+// W_d^-1/2 S_d W_d^-1/2 = U_d Lambda_d U_d^T for d = x, y:
+//   theta = (I x Q_y x Q_x) [ (L_z + lx + ly)^-1 (I x P_y x P_x) f ],
+//   P_d = U_d^T W_d^1/2,  Q_d = W_d^-1/2 U_d,  f = b / w = q / k + boundary terms,
+// where the middle factor is one tridiagonal solve along z per mode pair.
+// The mode products are FP64 GEMMs; these kernels gather f, solve along z and
+// scatter theta back.
 struct FdmBox {
   int a[3];                 // first free node per direction
   int m[3];                 // free nodes per direction
@@ -441,15 +442,63 @@ __global__ void __launch_bounds__(256) fdm_gather(ThermGeom g, FdmBox bx, const 
   }
 }
 
-__global__ void __launch_bounds__(256) fdm_divide(FdmBox bx, const double* __restrict__ lx,
-                                                  const double* __restrict__ ly,
-                                                  const double* __restrict__ lz, double* __restrict__ f) {
-  const size_t n = (size_t)bx.m[0] * bx.m[1] * bx.m[2];
-  for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (size_t)gridDim.x * 256) {
-    const int i = (int)(k % bx.m[0]);
-    const int j = (int)((k / bx.m[0]) % bx.m[1]);
-    const int l = (int)(k / ((size_t)bx.m[0] * bx.m[1]));
-    f[k] /= lx[i] + ly[j] + lz[l];
+// The z direction is not diagonalised: after the x and y transforms every
+// mode pair (i, j) leaves the tridiagonal system (A_z + (lx_i + ly_j) I) u = f
+// along z, A_z = W^-1 S the weighted 1-D operator (diagonal dg, off-diagonal
+// od[k] in row k).  It is diagonally dominant, so the Thomas algorithm solves
+// it without pivoting, in FP64.  f is overwritten by u; cp holds the
+// eliminated super-diagonal.  One thread per mode pair walks z (adjacent
+// threads touch adjacent addresses), loading kTriU planes at a time so that
+// several loads are in flight.
+constexpr int kTriU = 16;
+
+__global__ void __launch_bounds__(256) fdm_tri_z(FdmBox bx, const double* __restrict__ lx,
+                                                 const double* __restrict__ ly,
+                                                 const double* __restrict__ dg,
+                                                 const double* __restrict__ od,
+                                                 double* __restrict__ f, double* __restrict__ cp) {
+  const int m0 = bx.m[0], m2 = bx.m[2];
+  const size_t plane = (size_t)m0 * bx.m[1];
+  for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < plane; q += (size_t)gridDim.x * 256) {
+    const double s = lx[q % m0] + ly[q / m0];
+    double c = 0.0, d = 0.0;   // c'_{k-1}, d'_{k-1}
+    for (int k0 = 0; k0 < m2; k0 += kTriU) {
+      double fv[kTriU];
+#pragma unroll
+      for (int u = 0; u < kTriU; ++u)
+        fv[u] = k0 + u < m2 ? f[(size_t)(k0 + u) * plane + q] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kTriU; ++u) {
+        const int k = k0 + u;
+        if (k < m2) {
+          const double lk = k > 0 ? od[k] : 0.0;
+          const double uk = k + 1 < m2 ? od[k] : 0.0;
+          const double r = 1.0 / (dg[k] + s - lk * c);
+          c = uk * r;
+          d = (fv[u] - lk * d) * r;
+          f[(size_t)k * plane + q] = d;
+          cp[(size_t)k * plane + q] = c;
+        }
+      }
+    }
+    double x = 0.0;
+    for (int k1 = m2; k1 > 0; k1 -= kTriU) {   // planes k1 - 1 down to k1 - kTriU
+      double dv[kTriU], cv[kTriU];
+#pragma unroll
+      for (int u = 0; u < kTriU; ++u) {
+        const int k = k1 - 1 - u;
+        dv[u] = k >= 0 ? f[(size_t)k * plane + q] : 0.0;
+        cv[u] = k >= 0 ? cp[(size_t)k * plane + q] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kTriU; ++u) {
+        const int k = k1 - 1 - u;
+        if (k >= 0) {
+          x = dv[u] - cv[u] * x;
+          f[(size_t)k * plane + q] = x;
+        }
+      }
+    }
   }
 }
 

@@ -126,15 +126,21 @@ def thermal_fwd_adj(device, reps=2):
 
 
 FP64_MFMA_PEAK = 78.6e12
+HBM_PEAK = 8.0e12
 
 
-def _direct_flops(nx, ny, nzn, faces):
-    """Flops of the six FP64 GEMM mode products of one direct solve."""
+TRI_BYTES_PER_NODE = 48    # z sweep: read f; write d', c'; read d', c'; write u (FP64)
+
+
+def _direct_work(nx, ny, nzn, faces):
+    """Algorithmic work of one direct solve: flops of the four FP64 GEMM mode
+    products (x and y, forward and backward) and bytes of the tridiagonal
+    sweep along z, over the packed free nodes."""
     def free(n, lo, hi):
         return n - (faces.get(lo) == "oven") - (faces.get(hi) == "oven")
     m = [free(nx, "x-", "x+"), free(ny, "y-", "y+"), free(nzn, "z-", "z+")]
     prod = m[0] * m[1] * m[2]
-    return 2 * 2 * sum(md * prod for md in m)
+    return 2 * 2 * (m[0] + m[1]) * prod, TRI_BYTES_PER_NODE * prod
 
 
 def _heat_of_march(wl, device):
@@ -152,8 +158,10 @@ def _heat_of_march(wl, device):
 
 def thermal(device, reps=3):
     """Heat equation (open-top oven) for the heat source of a march.
-      direct  fast diagonalisation: FP64 GEMM mode products on MFMA; roofline
-              against the FP64 MFMA peak (the set-up, once per plan, is timed apart)
+      direct  diagonalisation in x and y (FP64 GEMM mode products on MFMA) and
+              tridiagonal solves along z (HBM-bound); its bound is the GEMM flops
+              at the FP64 MFMA peak plus the sweep's bytes at the HBM peak (the
+              set-up, once per plan, is timed apart)
       cg      Jacobi-PCG to a relative residual of 1e-6 from a cold start;
               convention 40 B per node and iteration"""
     import torch
@@ -176,11 +184,12 @@ def thermal(device, reps=3):
             t, _, _, res = th.solve(heat)
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t0) / reps
-        flops = _direct_flops(wl.nx, wl.ny, wl.nz + 1, setup["faces"])
+        flops, tri_bytes = _direct_work(wl.nx, wl.ny, wl.nz + 1, setup["faces"])
+        bound = flops / FP64_MFMA_PEAK + tri_bytes / HBM_PEAK
         out[f"direct_{wl.nx}x{wl.ny}x{wl.nz + 1}"] = {
             "nodes": nodes, "ms": round(sec * 1e3, 3), "first_solve_ms": round(first * 1e3, 2),
-            "residual": res, "gemm_tflops": round(flops / sec / 1e12, 2),
-            "frac_fp64_mfma": round(flops / sec / FP64_MFMA_PEAK, 4),
+            "residual": res, "gemm_flops": flops, "tri_bytes": tri_bytes,
+            "bound_ms": round(bound * 1e3, 3), "frac_of_bound": round(bound / sec, 4),
             "t_max_rise_K": round(float(t.max()) - workloads.T_OVEN, 4)}
         del th, t
     wl = workloads.c2_plain_c64()
