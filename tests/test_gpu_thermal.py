@@ -190,6 +190,31 @@ def test_non_square_grid_and_single_step(method):
     assert t_mid.shape == (1, 16, 64)
 
 
+@pytest.mark.parametrize("faces,nz", [
+    ({"z-": "oven"}, 8),                                   # oven on a z face
+    ({"z-": "oven", "z+": "oven"}, 2),                     # one free plane along z
+    ({"x-": "insulated", "x+": "insulated", "y-": "insulated", "y+": "insulated",
+      "z+": "oven"}, 12),                                  # zero shift for the (0, 0) mode
+    ({}, 5),                                               # convective faces only
+])
+def test_direct_solve_z_lines(faces, nz):
+    """The direct solver diagonalises x and y and eliminates along z, one
+    tridiagonal system per (x, y) mode pair.  Face layouts that change the z
+    system: ovens on z faces (fewer free planes, down to one), insulated x and
+    y faces (the (0, 0) mode adds nothing to the z diagonal, so the z system
+    alone must be regular), and convective faces only."""
+    from paper_2410_04994_amd import Thermal
+    p = dict(nx=16, ny=32, nz=nz, lx=0.5e-3, ly=0.8e-3, lcr=1.5e-3)
+    k_th, h_conv, t_inf, t_oven = 6.0, 3e3, 297.0, 335.0
+    rng = np.random.Generator(np.random.PCG64(31 + nz))
+    q = 1e9 * np.exp(rng.normal(size=thermal.grid_shape(p)))
+    ref = thermal.solve(p, thermal.ThermalParams(k_th, h_conv, t_inf, t_oven, faces), q)
+    th = Thermal(p, k_th, h_conv, t_inf, t_oven, faces, "c128", method="direct")
+    t, _, it, res = th.solve(torch.from_numpy(q).cuda())
+    assert it == 0 and res < 1e-11
+    assert np.max(np.abs(t.cpu().numpy() - ref)) < 1e-9 * np.ptp(ref)
+
+
 def test_every_node_on_an_oven():
     """Ovens on both z faces of a single step: no free node, T = T_oven."""
     from paper_2410_04994_amd import Thermal
