@@ -429,6 +429,11 @@ static int solve_direct(Therm& th, const R* heat, R* t_nodes, R* t_mid, char* ws
     hipLaunchKernelGGL((th_midplanes<R>), dim3(th.nblk), blk, 0, st, (const R*)t_nodes, plane,
                        plane * (size_t)(g.nzn - 1), t_mid);
   }
+  if (!resid_out) {
+    // no residual requested (the self-consistent loop): no check, no wait
+    const hipError_t le = hipGetLastError();
+    return le == hipSuccess ? SHG_OK : hip_fail(le, "direct solve");
+  }
   // residual of the node equations for the FP64 solution: |b - A theta| / |b|
   hipLaunchKernelGGL((th_residual<double, true, R>), dim3(th.nblk), blk, 0, st, g, heat,
                      (const double*)f1, f0, part);
@@ -437,7 +442,7 @@ static int solve_direct(Therm& th, const R* heat, R* t_nodes, R* t_mid, char* ws
   hipError_t e = hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "direct solve");
-  if (resid_out) *resid_out = hs[kBb] > 0.0 ? std::sqrt(hs[kRz] / hs[kBb]) : std::sqrt(hs[kRz]);
+  *resid_out = hs[kBb] > 0.0 ? std::sqrt(hs[kRz] / hs[kBb]) : std::sqrt(hs[kRz]);
   return SHG_OK;
 }
 
