@@ -196,6 +196,8 @@ def test_non_square_grid_and_single_step(method):
     ({"x-": "insulated", "x+": "insulated", "y-": "insulated", "y+": "insulated",
       "z+": "oven"}, 12),                                  # zero shift for the (0, 0) mode
     ({}, 5),                                               # convective faces only
+    ({"x-": "insulated", "x+": "insulated", "y-": "insulated", "y+": "insulated",
+      "z-": "insulated"}, 7),                              # one convective face, no oven
 ])
 def test_direct_solve_z_lines(faces, nz):
     """The direct solver diagonalises x and y and eliminates along z, one
