@@ -151,6 +151,26 @@ int shg_propagate(shg_plan *plan, void *a_f, void *a_sh, const double *dk_z,
                   const void *temp, int32_t s_begin, int32_t s_end,
                   void *workspace, double *powers, void *stream);
 
+/* shg_propagate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, hosts that forbid hipMalloc).  Same
+ * arguments and results as shg_propagate without `workspace`: the march's
+ * workspace (phase table, power partials, temperature phase) is a static
+ * device array of 4 MiB per GPU, held until the process ends.  The call
+ * allocates nothing and creates no graph: the passes are enqueued one by one
+ * on `stream` (so it can be recorded into a caller's graph).  Every call on a
+ * GPU shares that GPU's array, so calls that overlap on one GPU (concurrent
+ * streams or threads) race and must be serialised by the caller; nothing in
+ * the array needs to survive between calls.  The current device must be the
+ * plan's.  Timing mode (shg_plan_set_timing) does not apply.
+ * Errors: as shg_propagate; SHG_EINVAL also when shg_workspace_bytes(plan, 0)
+ * exceeds 4 MiB (nz above about 26000 for 512x512 complex128, about 78000
+ * for 512x512 complex64), when the current device is not the plan's,
+ * or for a plan with SHG_CHECK_FINITE; SHG_EDEVICE when the array's device
+ * address could not be obtained. */
+int shg_propagate_noalloc(shg_plan *plan, void *a_f, void *a_sh, const double *dk_z,
+                          const void *temp, int32_t s_begin, int32_t s_end, double *powers,
+                          void *stream);
+
 /* The whole march (steps [0, nz)) as shg_propagate, also writing the heat
  * source of Sec. 2.2, q = sum_j alpha_j I_j + beta_j I_j^2 with
  * I_j = eps0 c n_j |A_j|^2 / 2 [W/m^3], of the fields at every step boundary

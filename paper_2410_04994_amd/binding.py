@@ -65,6 +65,7 @@ _SIGS = {
     "shg_plan_destroy": (ctypes.c_int, [_VP]),
     "shg_workspace_bytes": (ctypes.c_size_t, [_VP, ctypes.c_int]),
     "shg_propagate": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP]),
+    "shg_propagate_noalloc": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _I32, _I32, _VP, _VP]),
     "shg_propagate_heat": (ctypes.c_int, [_VP] * 9),
     "shg_propagate_adjoint": (ctypes.c_int, [_VP] * 16 + [_VP]),
     "shg_propagate_batch": (ctypes.c_int, [_I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -258,6 +259,20 @@ class Plan:
             self._dk(dk_z), self._temp(temp), int(s_begin), int(s_end),
             self._ws_ptr(workspace, False), _ptr(powers, "powers", torch.float64, numel=2),
             _stream(stream)))
+        return powers
+
+    def propagate_noalloc(self, a_f, a_sh, powers, dk_z=None, temp=None, s_begin: int = 0,
+                          s_end: Optional[int] = None, stream=None):
+        """shg_propagate_noalloc: the march of `propagate` with the library's
+        static per-GPU workspace; the call allocates nothing (powers is a
+        caller-owned device double[2]).  Overlapping calls on one GPU race."""
+        torch = _torch()
+        if s_end is None:
+            s_end = self.params["nz"]
+        _check(load_library().shg_propagate_noalloc(
+            self.handle, self._field(a_f, "a_f"), self._field(a_sh, "a_sh"),
+            self._dk(dk_z), self._temp(temp), int(s_begin), int(s_end),
+            _ptr(powers, "powers", torch.float64, numel=2), _stream(stream)))
         return powers
 
     def propagate_heat(self, a_f, a_sh, dk_z=None, temp=None, heat=None, workspace=None,

@@ -107,8 +107,9 @@ int sticky_device_error();
 size_t forward_ws_bytes(const Plan& pl);
 int enqueue_forward(Plan& pl, void* a, void* b, const double* dk_z, int s0, int s1, void* ws,
                     double* powers, hipStream_t st);
+// timed = false launches without the per-kernel events of timing mode.
 int enqueue_forward_io(Plan& pl, const FwdIO& io, const double* dk_z, int s0, int s1, void* ws,
-                       double* powers, hipStream_t st, bool make_phase);
+                       double* powers, hipStream_t st, bool make_phase, bool timed = true);
 int ensure_own_ws(Plan& pl, size_t bytes);
 int propagate(Plan& pl, void* a_f, void* a_sh, const double* dk_z, const void* temp, int s0,
               int s1, void* ws, double* powers, hipStream_t st, void* heat);

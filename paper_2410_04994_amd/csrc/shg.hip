@@ -490,7 +490,8 @@ size_t forward_ws_bytes(const Plan& pl) {
 
 template <typename R>
 static int enqueue_forward_t(Plan& pl, const FwdIO& io, const double* dk_z, int s0, int s1,
-                             char* ws, double* powers, hipStream_t st, bool make_phase) {
+                             char* ws, double* powers, hipStream_t st, bool make_phase,
+                             bool timed) {
   const shg_params& p = pl.p;
   cx<R>* phase = (cx<R>*)ws;
   double* partials = (double*)(ws + align256((size_t)p.nz * 5 * sizeof(cx<R>)));
@@ -551,7 +552,7 @@ static int enqueue_forward_t(Plan& pl, const FwdIO& io, const double* dk_z, int 
   ca.tiles = p.nx / pl.col_tc;
   ca.conj_prop = 0;
   int rows = 1;
-  LaunchTimer tm{&pl};
+  LaunchTimer tm{timed ? &pl : nullptr};
   if (p.flags & SHG_SPLIT_LNL) {
     // L/2 - N - L/2: FFT_x, half-step column pass, then per step the whole
     // nonlinear step between IFFT_x and FFT_x and a column pass (half-step for
@@ -647,10 +648,11 @@ static int enqueue_forward_t(Plan& pl, const FwdIO& io, const double* dk_z, int 
 }
 
 int enqueue_forward_io(Plan& pl, const FwdIO& io, const double* dk_z, int s0, int s1, void* ws,
-                       double* powers, hipStream_t st, bool make_phase) {
+                       double* powers, hipStream_t st, bool make_phase, bool timed) {
   if (pl.dtype == SHG_C64)
-    return enqueue_forward_t<float>(pl, io, dk_z, s0, s1, (char*)ws, powers, st, make_phase);
-  return enqueue_forward_t<double>(pl, io, dk_z, s0, s1, (char*)ws, powers, st, make_phase);
+    return enqueue_forward_t<float>(pl, io, dk_z, s0, s1, (char*)ws, powers, st, make_phase,
+                                    timed);
+  return enqueue_forward_t<double>(pl, io, dk_z, s0, s1, (char*)ws, powers, st, make_phase, timed);
 }
 
 int launch_col(Plan& pl, void* a, void* b, int conj, hipStream_t st, bool half) {
@@ -835,6 +837,66 @@ int propagate(Plan& pl, void* a_f, void* a_sh, const double* dk_z, const void* t
   return SHG_OK;
 }
 
+// ---------------------------------------------------------------- static workspace
+// Workspace of shg_propagate_noalloc: a device array of fixed size, one copy
+// per GPU, held until the process ends.  Its name is only a host-side handle;
+// the device address comes from hipGetSymbolAddress, taken once per device
+// (with that device current) when the first plan is created there, and is the
+// only form passed to kernels.  Every call on a GPU shares that GPU's copy.
+constexpr size_t kStaticWsBytes = size_t(4) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticWsBytes];
+
+static std::mutex g_scratch_mu;
+static std::vector<void*> g_scratch_ptr;   // device address per device id
+static std::vector<int> g_scratch_state;   // 0 = not set up, 1 = ready, 2 = failed
+
+static void static_ws_setup(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= device) {
+    g_scratch_ptr.resize(device + 1, nullptr);
+    g_scratch_state.resize(device + 1, 0);
+  }
+  if (g_scratch_state[device]) return;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+  g_scratch_state[device] = e == hipSuccess ? 1 : 2;
+}
+
+static void* static_ws(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= (int)g_scratch_ptr.size() || g_scratch_state[device] != 1)
+    return nullptr;
+  return g_scratch_ptr[device];
+}
+
+static int propagate_noalloc(Plan& pl, void* a_f, void* a_sh, const double* dk_z,
+                             const void* temp, int s0, int s1, double* powers, hipStream_t st) {
+  if (!a_f || !a_sh) return fail(SHG_EINVAL, "a_f and a_sh must be non-NULL device pointers");
+  if (!(0 <= s0 && s0 < s1 && s1 <= pl.p.nz))
+    return fail(SHG_EINVAL, "step range [%d, %d) not within [0, nz=%d]", s0, s1, pl.p.nz);
+  if (checks_finite(pl))
+    return fail(SHG_EINVAL, "SHG_CHECK_FINITE is not available without allocation");
+  const size_t need = forward_ws_bytes(pl);
+  if (need > kStaticWsBytes)
+    return fail(SHG_EINVAL,
+                "plan needs %zu bytes of workspace (nz=%d, %dx%d); the static workspace holds "
+                "%zu bytes: use shg_propagate",
+                need, pl.p.nz, pl.p.nx, pl.p.ny, kStaticWsBytes);
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != pl.device)
+    return fail(SHG_EINVAL, "plan was created on device %d, current device is %d", pl.device, dev);
+  void* ws = static_ws(dev);
+  if (!ws) return fail(SHG_EDEVICE, "static workspace address unavailable on device %d", dev);
+  int rc = sticky_device_error();
+  if (rc) return rc;
+  FwdIO io{a_f, a_sh, a_f, a_sh, a_f, a_sh, nullptr};
+  io.temp = temp;
+  return enqueue_forward_io(pl, io, dk_z, s0, s1, ws, powers, st, true, false);
+}
+
 }  // namespace shg
 
 using namespace shg;
@@ -861,6 +923,7 @@ int shg_plan_create(shg_plan** out, const shg_params* p, shg_dtype dtype) {
     g_last_error = msg;
     return rc;
   }
+  static_ws_setup(pl->device);
   pl->magic = Plan::kMagic;
   *out = reinterpret_cast<shg_plan*>(pl);
   return ok();
@@ -890,6 +953,16 @@ int shg_propagate(shg_plan* plan, void* a_f, void* a_sh, const double* dk_z, con
   Plan* pl = reinterpret_cast<Plan*>(plan);
   rc = propagate(*pl, a_f, a_sh, dk_z, temp, s_begin, s_end, workspace, powers,
                  (hipStream_t)stream, nullptr);
+  return rc ? rc : ok();
+}
+
+int shg_propagate_noalloc(shg_plan* plan, void* a_f, void* a_sh, const double* dk_z,
+                          const void* temp, int32_t s_begin, int32_t s_end, double* powers,
+                          void* stream) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  Plan* pl = reinterpret_cast<Plan*>(plan);
+  rc = propagate_noalloc(*pl, a_f, a_sh, dk_z, temp, s_begin, s_end, powers, (hipStream_t)stream);
   return rc ? rc : ok();
 }
 

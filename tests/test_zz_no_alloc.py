@@ -1,0 +1,78 @@
+"""shg_propagate_noalloc: the march with the library's static per-GPU workspace.
+
+It runs the same passes as shg_propagate, so on the same inputs its fields and
+powers must equal those of shg_propagate (the existing entry point) bit for
+bit.  Two calls in a row, the second on a smaller grid with fewer steps, check
+that nothing left in the shared array by the first call leaks into the second.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import inputs, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _run_both(wl, temp=None):
+    import torch
+    from paper_2410_04994_amd import Plan
+
+    plan = Plan(wl.params(), "c64")
+    a0, b0 = inputs(wl)
+    tt = None
+    if temp is not None:
+        tt = torch.from_numpy(np.ascontiguousarray(temp, np.float32)).cuda()
+    # existing entry point (caller-owned workspace)
+    a_ref = torch.from_numpy(a0).cuda()
+    b_ref = torch.from_numpy(b0).cuda()
+    p_ref = plan.propagate(a_ref, b_ref, temp=tt, workspace=plan.workspace())
+    # static-workspace entry point, all buffers allocated before the call
+    a = torch.from_numpy(a0).cuda()
+    b = torch.from_numpy(b0).cuda()
+    pw = torch.empty(2, dtype=torch.float64, device="cuda")
+    plan.propagate_noalloc(a, b, pw, temp=tt)
+    torch.cuda.synchronize()
+    out = [t.cpu().numpy() for t in (a, b, pw, a_ref, b_ref, p_ref)]
+    plan.close()
+    return out
+
+
+def test_noalloc_equals_propagate_on_two_calls_in_a_row():
+    import torch
+
+    assert torch.cuda.is_available()
+    # first call: 128 x 128, 80 steps, with a temperature field (the per-cell
+    # thermal phase lives in the static workspace too)
+    wl1 = workloads.c5_thermal_c64().with_(nx=128, ny=128, nz=80)
+    t1 = workloads.radial_temperature_profile(wl1)
+    # second call: a smaller grid and fewer steps, no temperature field
+    wl2 = workloads.c2_plain_c64().with_(nx=64, ny=64, nz=30)
+    for label, wl, temp in (("128x128x80 with T", wl1, t1), ("64x64x30", wl2, None)):
+        print(f"noalloc case {label}", flush=True)
+        a, b, pw, a_ref, b_ref, p_ref = _run_both(wl, temp)
+        print(f"  F rel={rel(a, a_ref):.2e} SH rel={rel(b, b_ref):.2e} powers {pw} vs {p_ref}")
+        assert np.array_equal(a, a_ref), label
+        assert np.array_equal(b, b_ref), label
+        assert np.array_equal(pw, p_ref), label
+        assert np.abs(b).max() > 0
+
+
+def test_noalloc_rejects_a_workspace_beyond_the_static_array():
+    import torch
+    from paper_2410_04994_amd import Plan
+    from paper_2410_04994_amd.binding import ShgError
+
+    # 512 x 512 complex128 needs 2 MiB for the thermal phase plus 80 B per
+    # step of phase table: above 4 MiB at nz = 30000 (rejected before launch)
+    wl = workloads.c2_plain_c64().with_(nx=512, ny=512, nz=30000)
+    plan = Plan(wl.params(), "c128")
+    assert plan.workspace_bytes() > 4 << 20
+    a = torch.zeros((512, 512), dtype=torch.complex128, device="cuda")
+    b = torch.zeros_like(a)
+    pw = torch.empty(2, dtype=torch.float64, device="cuda")
+    with pytest.raises(ShgError, match="SHG_EINVAL.*static workspace"):
+        plan.propagate_noalloc(a, b, pw)
+    plan.close()
