@@ -1,5 +1,7 @@
 """Batched march: every instance equals its own single-instance march, sampled
 instances match the oracle, graph replays are deterministic (needs the GPU)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -185,8 +187,10 @@ def test_batch_rejects_mixed_split_orders():
 def test_full_size_sweep_against_single_marches_and_oracle():
     """The 512-instance sweep at its full step counts (64/128/256 in 1:2:1, nz
     in [200, 1000]) with the schedules the benchmark uses: 16 sampled
-    instances equal their own single-instance marches bit for bit, and the
-    shortest instance of each size matches the oracle."""
+    instances equal their own single-instance marches bit for bit, the
+    shortest instance of each size matches the oracle, and so does the longest
+    (the oracle's results for those are stored by
+    tests/golden/make_full_size_refs.py)."""
     from paper_2410_04994_amd import Plan
     wls = workloads.c3_batch()
     print(f"case: c3 sweep, {len(wls)} instances, full nz", flush=True)
@@ -206,3 +210,18 @@ def test_full_size_sweep_against_single_marches_and_oracle():
         w = wls[idx]
         ref = run_oracle(w, ins[idx][0], ins[idx][1])
         compare(w, (A[idx], B[idx], pw[idx]), ref, "c64", f"sweep[{idx}] {size}x{size}x{w.nz}")
+    longest = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                   "full_size", "c3_longest.npz"))
+    for size in (64, 128, 256):
+        idx = int(longest[f"index_{size}"])
+        w = wls[idx]
+        assert w.nx == size and w.nz == int(longest[f"nz_{size}"])
+        assert w.nz == max(x.nz for x in wls if x.nx == size)
+        a_in = ins[idx][0].astype(np.complex128)
+        fp = np.array([float(np.sum(np.abs(a_in) ** 2)), a_in[size // 2, size // 2].real,
+                       a_in[size // 2, size // 2].imag])
+        assert np.allclose(fp, longest[f"input_{size}"], rtol=1e-12, atol=0)
+        pr = longest[f"powers_{size}"]
+        ref = {"a_f": longest[f"a_f_{size}"].astype(np.complex128),
+               "a_sh": longest[f"a_sh_{size}"].astype(np.complex128), "p_f": pr[0], "p_sh": pr[1]}
+        compare(w, (A[idx], B[idx], pw[idx]), ref, "c64", f"longest sweep[{idx}] {size}x{size}x{w.nz}")

@@ -235,9 +235,7 @@ def random_real(shape, seed: int, scale: float = 1.0) -> np.ndarray:
     return rng.normal(size=shape) * scale
 
 
-def radial_temperature_profile(wl: Workload) -> np.ndarray:
-    """Synthetic midplane temperature samples T[s, y, x] (float64) for the
-    thermal-lens workload: T0 + dT(z_s + dz/2) exp(-2 r^2 / w_T^2)."""
+def _radial_temperature_parts(wl: Workload):
     ex = wl.extra
     t0, peak, wt = ex["t0"], ex["dT_peak"], ex["wT_over_w0"] * wl.w0
     dx, dy, dz = wl.lx / wl.nx, wl.ly / wl.ny, wl.lcr / wl.nz
@@ -246,7 +244,39 @@ def radial_temperature_profile(wl: Workload) -> np.ndarray:
     r2 = y[:, None] ** 2 + x[None, :] ** 2
     zmid = (np.arange(wl.nz) + 0.5) * dz
     dT = peak * np.exp(-wl.alpha_sh * zmid)
-    return t0 + dT[:, None, None] * np.exp(-2.0 * r2 / wt ** 2)[None, :, :]
+    return t0, dT, np.exp(-2.0 * r2 / wt ** 2)
+
+
+def radial_temperature_profile(wl: Workload) -> np.ndarray:
+    """Synthetic midplane temperature samples T[s, y, x] (float64) for the
+    thermal-lens workload: T0 + dT(z_s + dz/2) exp(-2 r^2 / w_T^2)."""
+    t0, dT, g = _radial_temperature_parts(wl)
+    return t0 + dT[:, None, None] * g[None, :, :]
+
+
+class RadialTemperature:
+    """The same samples as radial_temperature_profile, built one step plane at a
+    time (T[s] is bitwise the plane s of the whole array), rounded to `dtype`
+    when given: the [nz][ny][nx] field of the 512 x 512 x 2000 workload is
+    2.1 GB in float32 and need not be held in float64."""
+
+    def __init__(self, wl: Workload, dtype=None):
+        self.t0, self.dT, self.g = _radial_temperature_parts(wl)
+        self.dtype = dtype
+        self.shape = (wl.nz, wl.ny, wl.nx)
+
+    def __len__(self):
+        return self.shape[0]
+
+    def __getitem__(self, s: int) -> np.ndarray:
+        plane = self.t0 + self.dT[s] * self.g
+        return plane if self.dtype is None else plane.astype(self.dtype)
+
+    def materialise(self, dtype=np.float32) -> np.ndarray:
+        out = np.empty(self.shape, dtype)
+        for s in range(self.shape[0]):
+            out[s] = self[s]
+        return out
 
 
 CONFIGS = {
