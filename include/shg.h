@@ -65,9 +65,9 @@ enum {
   SHG_EUNSUPPORTED = 2, /* valid but not built here (e.g. grid size)        */
   SHG_ENOMEM = 3,       /* device allocation failed                          */
   SHG_EDEVICE = 4,      /* HIP runtime error, including earlier device faults */
-  SHG_ESTATE = 5,       /* NULL or destroyed plan                            */
-  SHG_ENONFINITE = 6    /* SHG_CHECK_FINITE found NaN or Inf (message says
+  SHG_ENONFINITE = 5,   /* SHG_CHECK_FINITE found NaN or Inf (message says
                            which array, input or output)                     */
+  SHG_ESTATE = 6        /* NULL or destroyed plan                            */
 };
 
 /* flags */
@@ -140,13 +140,17 @@ size_t shg_workspace_bytes(const shg_plan *plan, int for_adjoint);
  *   dk_z       [nz] double per-step mismatch, or NULL for params.dk0
  *   temp       [nz][ny][nx] mid-plane temperature samples in the plan's real
  *              type (float for C64, double for C128), or NULL for none
- *   workspace  shg_workspace_bytes(plan, 0) bytes, or NULL to use a buffer
- *              the plan allocates on first use and keeps
+ *   workspace  shg_workspace_bytes(plan, 0) bytes, or NULL to use the
+ *              plan's own buffer (allocated by shg_plan_create)
  *   powers     double[2] {P_F, P_SH} at z = s_end dz (P = int eps0 c n |A|^2/2
  *              dA, Sec. 2.2), or NULL
  *   stream     hipStream_t as void*
+ * The call allocates no device memory.  Outside stream capture it replays a
+ * HIP graph of the march that it captures (on a private stream) the first
+ * time it sees a set of arguments; under the caller's capture it enqueues the
+ * passes themselves, so it can be recorded into the caller's graph.
  * Errors: SHG_ESTATE, SHG_EINVAL (NULL field, 0 <= s_begin < s_end <= nz
- * violated), SHG_ENOMEM, SHG_EDEVICE, SHG_ENONFINITE (SHG_CHECK_FINITE). */
+ * violated), SHG_EDEVICE, SHG_ENONFINITE (SHG_CHECK_FINITE). */
 int shg_propagate(shg_plan *plan, void *a_f, void *a_sh, const double *dk_z,
                   const void *temp, int32_t s_begin, int32_t s_end,
                   void *workspace, double *powers, void *stream);
@@ -219,11 +223,20 @@ int shg_propagate_adjoint(shg_plan *plan, const void *a_f_in, const void *a_sh_i
  *   plans[i], a_f[i], a_sh[i]  as for shg_propagate (fields updated in place)
  *   dk_z[i]                    per-instance [nz_i] profile, or NULL entries /
  *                              NULL array for the plans' dk0
- *   workspace                  shg_batch_workspace_bytes(...) bytes, or NULL
- *                              for a library-owned buffer kept by plans[0]
+ *   workspace                  shg_batch_workspace_bytes(...) bytes (phase
+ *                              tables and power partials, rewritten by every
+ *                              call), or NULL for a buffer kept by plans[0]
  *   powers                     [n][2] double exit powers, or NULL
+ * The first call with a set of arguments (plans, fields, profiles, workspace,
+ * powers) uploads the instance descriptors into a table owned by plans[0]
+ * (allocated or grown then, as is the NULL-workspace buffer), runs the batch
+ * and captures it into a graph that later calls with the same arguments
+ * replay.  Such a first call synchronises the stream and cannot be recorded
+ * into a caller's graph: under stream capture only an already-seen set of
+ * arguments is accepted (it enqueues the launches, allocating nothing).
  * Errors: SHG_EINVAL (n < 1, NULL arrays/entries, mixed dtypes, temperature
- * flags), SHG_ENOMEM, SHG_EDEVICE. */
+ * flags, new arguments or a missing NULL-workspace buffer under stream
+ * capture), SHG_ENOMEM, SHG_EDEVICE. */
 int shg_propagate_batch(int32_t n, shg_plan *const *plans, void *const *a_f,
                         void *const *a_sh, const double *const *dk_z,
                         void *workspace, double *powers, void *stream);

@@ -15,13 +15,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libshg.so")
 
 SHG_C64, SHG_C128 = 0, 1
-SHG_OK, SHG_EINVAL, SHG_EUNSUPPORTED, SHG_ENOMEM, SHG_EDEVICE, SHG_ESTATE, SHG_ENONFINITE = range(7)
+SHG_OK, SHG_EINVAL, SHG_EUNSUPPORTED, SHG_ENOMEM, SHG_EDEVICE, SHG_ENONFINITE, SHG_ESTATE = range(7)
 SHG_UNDEPLETED = 1 << 0
 SHG_NO_GRAPH = 1 << 1
 SHG_SPLIT_LNL = 1 << 2
 SHG_CHECK_FINITE = 1 << 3
 ERROR_NAMES = {0: "SHG_OK", 1: "SHG_EINVAL", 2: "SHG_EUNSUPPORTED", 3: "SHG_ENOMEM",
-               4: "SHG_EDEVICE", 5: "SHG_ESTATE", 6: "SHG_ENONFINITE"}
+               4: "SHG_EDEVICE", 5: "SHG_ENONFINITE", 6: "SHG_ESTATE"}
 
 
 class ShgError(RuntimeError):

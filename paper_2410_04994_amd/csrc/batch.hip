@@ -153,7 +153,7 @@ struct BatchPlanInfo {
   std::vector<Group> groups;
   std::vector<std::vector<int>> branches;   // group indices per stream
   std::vector<int> order;     // descriptor slot -> caller index
-  size_t desc_bytes = 0, phase_off = 0, part_off = 0, total = 0;
+  size_t total = 0;   // workspace bytes: per-instance phase tables and power partials
   std::vector<size_t> phase_at, part_at;   // per caller index
 };
 
@@ -162,7 +162,10 @@ struct BatchCache {
   std::vector<const void*> key;
   hipGraphExec_t exec = nullptr;
   hipStream_t cap = nullptr;
-  void* dev_desc = nullptr;   // inside the workspace; remembered for the key
+  // descriptor table in device memory owned by the cache (not the caller's
+  // workspace, which another batch may fill between two replays)
+  void* desc = nullptr;
+  size_t desc_cap = 0;
   // side streams for the size groups (parallel branches of the captured graph)
   hipStream_t side[kMaxBranches] = {};
   hipEvent_t fork = nullptr, join[kMaxBranches] = {};
@@ -178,7 +181,6 @@ static int build_info(int n, shg_plan* const* plans, BatchPlanInfo& bi) {
   const Plan& p0 = *reinterpret_cast<const Plan*>(plans[0]);
   bi.lnl = (p0.p.flags & SHG_SPLIT_LNL) != 0;
   const size_t csize = 2 * (size_t)p0.real_bytes;
-  const size_t inst_bytes = p0.dtype == SHG_C64 ? sizeof(BatchInst<float>) : sizeof(BatchInst<double>);
   bi.groups.clear();
   bi.order.clear();
   for (auto& kv : by) {
@@ -198,8 +200,7 @@ static int build_info(int n, shg_plan* const* plans, BatchPlanInfo& bi) {
     }
     bi.groups.push_back(g);
   }
-  size_t off = align256((size_t)n * inst_bytes);
-  bi.desc_bytes = off;
+  size_t off = 0;
   bi.phase_at.assign(n, 0);
   bi.part_at.assign(n, 0);
   for (int i = 0; i < n; ++i) {
@@ -251,8 +252,8 @@ template <typename R>
 static int enqueue_batch(int n, shg_plan* const* plans, void* const* a_f, void* const* a_sh,
                          const double* const* dk_z, char* ws, double* powers,
                          const BatchPlanInfo& bi, hipStream_t st, bool upload,
-                         const BatchCache* side) {
-  BatchInst<R>* dev = (BatchInst<R>*)ws;
+                         const BatchCache* side, void* desc) {
+  BatchInst<R>* dev = (BatchInst<R>*)desc;
   if (upload) {
     std::vector<BatchInst<R>> host(n);
     for (int slot = 0; slot < n; ++slot) {
@@ -375,6 +376,7 @@ void free_batch(Plan& pl) {
     if (bc->join[b]) (void)hipEventDestroy(bc->join[b]);
   }
   if (bc->fork) (void)hipEventDestroy(bc->fork);
+  if (bc->desc) (void)hipFree(bc->desc);
   delete bc;
   pl.batch = nullptr;
 }
@@ -387,15 +389,22 @@ static int run_batch(int n, shg_plan* const* plans, void* const* a_f, void* cons
   BatchPlanInfo bi;
   if ((rc = build_info(n, plans, bi))) return rc;
   Plan& p0 = *reinterpret_cast<Plan*>(plans[0]);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(st, &cs);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+  const bool capturing = cs != hipStreamCaptureStatusNone;
   if (!ws) {
     if (!p0.batch_ws || p0.batch_ws_bytes < bi.total) {
+      if (capturing)
+        return fail(SHG_EINVAL, "no workspace under stream capture: pass one, or run the batch "
+                                "once outside capture first");
       if (p0.batch_ws) {
-        hipError_t e = hipDeviceSynchronize();
+        e = hipDeviceSynchronize();
         if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
         (void)hipFree(p0.batch_ws);
         p0.batch_ws = nullptr;
       }
-      hipError_t e = hipMalloc(&p0.batch_ws, bi.total);
+      e = hipMalloc(&p0.batch_ws, bi.total);
       if (e != hipSuccess) {
         p0.batch_ws = nullptr;
         return hip_fail(e, "hipMalloc(batch workspace)");
@@ -404,12 +413,13 @@ static int run_batch(int n, shg_plan* const* plans, void* const* a_f, void* cons
     }
     ws = p0.batch_ws;
   }
-  // cache key: every argument that is baked into the descriptors or the graph
+  // cache key: every argument that is baked into the descriptors or the graph;
+  // plans enter by serial number (a destroyed plan's address can be reused)
   std::vector<const void*> key;
-  key.reserve(4 * n + 4);
+  key.reserve(5 * n + 2);
   for (int i = 0; i < n; ++i) {
     const Plan* pl = reinterpret_cast<const Plan*>(plans[i]);
-    key.push_back(pl);
+    key.push_back(reinterpret_cast<const void*>((uintptr_t)pl->serial));
     key.push_back(a_f[i]);
     key.push_back(a_sh[i]);
     key.push_back(dk_z ? dk_z[i] : nullptr);
@@ -420,10 +430,12 @@ static int run_batch(int n, shg_plan* const* plans, void* const* a_f, void* cons
   key.push_back(powers);
   if (!p0.batch) p0.batch = new BatchCache();
   BatchCache* bc = (BatchCache*)p0.batch;
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  hipError_t e = hipStreamIsCapturing(st, &cs);
-  if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
   const bool same = bc->exec && bc->key == key;
+  if (capturing && !same)
+    // the caller records this call into its own graph: the descriptors must
+    // already be on the device (uploading needs a host synchronisation)
+    return fail(SHG_EINVAL, "batch arguments changed while the stream is being captured; "
+                            "run the batch once outside capture first");
   if (bi.branches.size() > 1 && !bc->fork) {
     for (int b = 0; b < kMaxBranches && e == hipSuccess; ++b) {
       e = hipStreamCreateWithFlags(&bc->side[b], hipStreamNonBlocking);
@@ -445,27 +457,41 @@ static int run_batch(int n, shg_plan* const* plans, void* const* a_f, void* cons
   const BatchCache* side = bc->fork ? bc : nullptr;
   auto enqueue = [&](hipStream_t s, bool upload) {
     return p0.dtype == SHG_C64
-               ? enqueue_batch<float>(n, plans, a_f, a_sh, dk_z, (char*)ws, powers, bi, s, upload, side)
-               : enqueue_batch<double>(n, plans, a_f, a_sh, dk_z, (char*)ws, powers, bi, s, upload, side);
+               ? enqueue_batch<float>(n, plans, a_f, a_sh, dk_z, (char*)ws, powers, bi, s, upload,
+                                      side, bc->desc)
+               : enqueue_batch<double>(n, plans, a_f, a_sh, dk_z, (char*)ws, powers, bi, s,
+                                       upload, side, bc->desc);
   };
-  if (cs != hipStreamCaptureStatusNone) {
-    // the caller records this call into its own graph: the descriptors must
-    // already be on the device (uploading needs a host synchronisation)
-    if (!same)
-      return fail(SHG_EINVAL, "batch arguments changed while the stream is being captured; "
-                              "run the batch once outside capture first");
-    return enqueue(st, false);
-  }
-  if (p0.p.flags & SHG_NO_GRAPH) return enqueue(st, true);
-  if (same) {
+  if (capturing) return enqueue(st, false);
+  if (same && !(p0.p.flags & SHG_NO_GRAPH)) {
     e = hipGraphLaunch(bc->exec, st);
     return e == hipSuccess ? SHG_OK : hip_fail(e, "hipGraphLaunch");
   }
-  // upload descriptors, then capture the launch sequence on a private stream
+  // new arguments (or no graph): drop the old graph and key, then upload the
+  // descriptors into the cache's own table
   if (bc->exec) {
     (void)hipGraphExecDestroy(bc->exec);
     bc->exec = nullptr;
   }
+  bc->key.clear();
+  const size_t desc_bytes =
+      (size_t)n * (p0.dtype == SHG_C64 ? sizeof(BatchInst<float>) : sizeof(BatchInst<double>));
+  if (bc->desc_cap < desc_bytes) {
+    if (bc->desc) {
+      e = hipDeviceSynchronize();
+      if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+      (void)hipFree(bc->desc);
+      bc->desc = nullptr;
+      bc->desc_cap = 0;
+    }
+    e = hipMalloc(&bc->desc, desc_bytes);
+    if (e != hipSuccess) {
+      bc->desc = nullptr;
+      return hip_fail(e, "hipMalloc(batch descriptors)");
+    }
+    bc->desc_cap = desc_bytes;
+  }
+  if (p0.p.flags & SHG_NO_GRAPH) return enqueue(st, true);
   if (!bc->cap) {
     e = hipStreamCreateWithFlags(&bc->cap, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");

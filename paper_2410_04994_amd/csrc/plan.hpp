@@ -30,6 +30,7 @@ struct GraphKey {
 struct Plan {
   static constexpr uint64_t kMagic = 0x5348475f504c414eull;  // "SHG_PLAN"
   uint64_t magic = 0;
+  uint64_t serial = 0;           // unique per plan created in this process
   shg_params p{};
   shg_dtype dtype = SHG_C64;
   int device = 0;
@@ -52,14 +53,16 @@ struct Plan {
   int adj_e = 0, adj_wg = 0;     // adjoint row pass
   int b_row_e = 0, b_row_wg = 0, b_col_e = 0, b_col_tc = 1;   // schedule inside batches
   int col_e = 0, col_tc = 1;
-  // library-owned workspaces
+  // library-owned workspaces: the forward one is allocated with the plan (so
+  // shg_propagate without a workspace allocates nothing), the batch one by the
+  // first batch that needs it
   void* own_ws = nullptr;
   size_t own_ws_bytes = 0;
   void* batch_ws = nullptr;
   size_t batch_ws_bytes = 0;
   // cached forward graph
   hipStream_t cap_stream = nullptr;
-  int* finite_flag = nullptr;  // device int of the SHG_CHECK_FINITE scans (allocated on first use)
+  int* finite_flag = nullptr;  // device int of the SHG_CHECK_FINITE scans (plans with the flag)
   hipGraphExec_t gexec = nullptr;
   GraphKey gkey{};
   // optional per-kernel timing (kind 0 = row pass, 1 = column pass)
@@ -110,7 +113,6 @@ int enqueue_forward(Plan& pl, void* a, void* b, const double* dk_z, int s0, int 
 // timed = false launches without the per-kernel events of timing mode.
 int enqueue_forward_io(Plan& pl, const FwdIO& io, const double* dk_z, int s0, int s1, void* ws,
                        double* powers, hipStream_t st, bool make_phase, bool timed = true);
-int ensure_own_ws(Plan& pl, size_t bytes);
 int propagate(Plan& pl, void* a_f, void* a_sh, const double* dk_z, const void* temp, int s0,
               int s1, void* ws, double* powers, hipStream_t st, void* heat);
 size_t align256(size_t v);

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -447,6 +448,21 @@ int build_plan(Plan& pl) {
   default_schedule(pl);
   if (pl.row_e == 0 || pl.col_e == 0)
     return fail(SHG_EUNSUPPORTED, "no built schedule for nx=%d ny=%d", p.nx, p.ny);
+  // the forward workspace and the finiteness flag are allocated here, so the
+  // march itself never allocates (and can be recorded under stream capture)
+  pl.own_ws_bytes = forward_ws_bytes(pl);
+  hipError_t e = hipMalloc(&pl.own_ws, pl.own_ws_bytes);
+  if (e != hipSuccess) {
+    pl.own_ws = nullptr;
+    return hip_fail(e, "hipMalloc(forward workspace)");
+  }
+  if (p.flags & SHG_CHECK_FINITE) {
+    e = hipMalloc((void**)&pl.finite_flag, sizeof(int));
+    if (e != hipSuccess) {
+      pl.finite_flag = nullptr;
+      return hip_fail(e, "hipMalloc(finite flag)");
+    }
+  }
   return SHG_OK;
 }
 
@@ -705,23 +721,6 @@ int enqueue_forward_temp(Plan& pl, void* a, void* b, const double* dk_z, const v
   return enqueue_forward_io(pl, io, dk_z, s0, s1, ws, powers, st, true);
 }
 
-int ensure_own_ws(Plan& pl, size_t bytes) {
-  if (pl.own_ws && pl.own_ws_bytes >= bytes) return SHG_OK;
-  if (pl.own_ws) {
-    hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    (void)hipFree(pl.own_ws);
-    pl.own_ws = nullptr;
-  }
-  hipError_t e = hipMalloc(&pl.own_ws, bytes);
-  if (e != hipSuccess) {
-    pl.own_ws = nullptr;
-    return hip_fail(e, "hipMalloc(workspace)");
-  }
-  pl.own_ws_bytes = bytes;
-  return SHG_OK;
-}
-
 // Replays a cached graph of the whole launch sequence when the arguments are
 // the same as last time; otherwise captures a new one on a private stream.
 static int run_forward(Plan& pl, void* a, void* b, const double* dk_z, const void* temp, int s0,
@@ -787,13 +786,7 @@ int check_finite(Plan& pl, const void* data, size_t count, bool dbl, const char*
   if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
   if (cs != hipStreamCaptureStatusNone)
     return fail(SHG_EINVAL, "SHG_CHECK_FINITE scans synchronise the stream: not under capture");
-  if (!pl.finite_flag) {
-    e = hipMalloc(&pl.finite_flag, sizeof(int));
-    if (e != hipSuccess) {
-      pl.finite_flag = nullptr;
-      return hip_fail(e, "hipMalloc(finite flag)");
-    }
-  }
+  if (!pl.finite_flag) return fail(SHG_ESTATE, "plan has no finiteness flag");
   const dim3 grid((unsigned)std::min<size_t>(4096, (count + 255) / 256));
   hipLaunchKernelGGL(flag_clear, dim3(1), dim3(64), 0, st, pl.finite_flag);
   if (dbl || pl.dtype == SHG_C128)
@@ -825,10 +818,7 @@ int propagate(Plan& pl, void* a_f, void* a_sh, const double* dk_z, const void* t
         (rc = check_finite(pl, temp, (size_t)pl.p.nz * field / 2, false, "temp", st)))
       return rc;
   }
-  if (!ws) {
-    if ((rc = ensure_own_ws(pl, forward_ws_bytes(pl)))) return rc;
-    ws = pl.own_ws;
-  }
+  if (!ws) ws = pl.own_ws;
   rc = run_forward(pl, a_f, a_sh, dk_z, temp, s0, s1, ws, powers, st, heat);
   if (rc || !checks_finite(pl)) return rc;
   if ((rc = check_finite(pl, a_f, field, false, "the march's output a_f", st)) ||
@@ -912,6 +902,8 @@ int shg_plan_create(shg_plan** out, const shg_params* p, shg_dtype dtype) {
   if (rc) return rc;
   Plan* pl = new (std::nothrow) Plan();
   if (!pl) return fail(SHG_ENOMEM, "host allocation failed");
+  static std::atomic<uint64_t> next_serial{1};
+  pl->serial = next_serial.fetch_add(1);
   pl->p = *p;
   pl->dtype = dtype;
   (void)hipGetDevice(&pl->device);

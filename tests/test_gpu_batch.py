@@ -225,3 +225,54 @@ def test_full_size_sweep_against_single_marches_and_oracle():
         ref = {"a_f": longest[f"a_f_{size}"].astype(np.complex128),
                "a_sh": longest[f"a_sh_{size}"].astype(np.complex128), "p_f": pr[0], "p_sh": pr[1]}
         compare(w, (A[idx], B[idx], pw[idx]), ref, "c64", f"longest sweep[{idx}] {size}x{size}x{w.nz}")
+
+
+def test_two_batches_alternating_through_one_caller_workspace():
+    """Two different batches share one caller workspace and alternate.  Each
+    batch's cached graph reads its descriptors from a table the library owns,
+    so a replay never sees the other batch's descriptors: every instance stays
+    bit for bit equal to its single-instance march."""
+    from paper_2410_04994_amd import Plan, propagate_batch, batch_workspace_bytes
+    batches = [small_batch(n=5, seed=21, max_nz=10), small_batch(n=7, seed=22, max_nz=12)]
+    plans = [[Plan(w.params(), "c64") for w in wls] for wls in batches]
+    ins = [[inputs(w) for w in wls] for wls in batches]
+    singles = []
+    for wls, ps, xs in zip(batches, plans, ins):
+        out = []
+        for w, p, (a0, b0) in zip(wls, ps, xs):
+            single = Plan(w.params(), "c64")
+            single.set_schedule(*batch_schedule(p))
+            a, b = torch.from_numpy(a0).cuda(), torch.from_numpy(b0).cuda()
+            pw = single.propagate(a, b)
+            torch.cuda.synchronize()
+            out.append((a.cpu().numpy(), b.cpu().numpy(), pw.cpu().numpy()))
+        singles.append(out)
+    nbytes = max(batch_workspace_bytes(ps) for ps in plans)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    for rnd in range(3):
+        for k in (0, 1):
+            a = [torch.from_numpy(x[0]).cuda() for x in ins[k]]
+            b = [torch.from_numpy(x[1]).cuda() for x in ins[k]]
+            pw = propagate_batch(plans[k], a, b, workspace=ws)
+            torch.cuda.synchronize()
+            for i, (sa, sb, sp) in enumerate(singles[k]):
+                assert np.array_equal(a[i].cpu().numpy(), sa), (rnd, k, i)
+                assert np.array_equal(b[i].cpu().numpy(), sb), (rnd, k, i)
+                assert np.array_equal(pw[i].cpu().numpy(), sp), (rnd, k, i)
+
+
+def test_batch_without_workspace_is_refused_under_capture_before_its_first_run():
+    """A batch whose library-owned workspace does not exist yet would have to
+    allocate it: under stream capture that is refused with SHG_EINVAL instead."""
+    from paper_2410_04994_amd import Plan, ShgError, propagate_batch
+    wls = small_batch(n=3, seed=23, max_nz=6)
+    plans = [Plan(w.params(), "c64") for w in wls]
+    a = [torch.from_numpy(inputs(w)[0]).cuda() for w in wls]
+    b = [torch.zeros_like(x) for x in a]
+    pw = torch.empty((3, 2), dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with pytest.raises(ShgError, match="SHG_EINVAL.*capture"):
+        with torch.cuda.graph(graph, stream=s, capture_error_mode="relaxed"):
+            propagate_batch(plans, a, b, powers=pw, stream=s)
+    torch.cuda.synchronize()

@@ -464,3 +464,30 @@ def test_pointwise_nonlinear_step_on_random_states(dtype):
     # the nonlinearity acted on every cell
     lin = run_oracle(wl.with_(d_eff=0.0, beta_f=0.0, beta_sh=0.0), a0, b0, dk_z=dk)
     assert rel(ref["a_sh"], lin["a_sh"]) > 1e-2
+
+
+def test_march_without_workspace_records_under_stream_capture():
+    """shg_propagate without a workspace allocates nothing: the plan allocated
+    its forward workspace when it was created.  So the call can be recorded
+    into a caller's HIP graph (any allocation would end the capture with an
+    error).  Every replay, with eager work and synchronisations between the
+    replays, equals the eager march bit for bit."""
+    from paper_2410_04994_amd import Plan
+    wl = workloads.c2_plain_c64().with_(nx=64, ny=64, nz=24)
+    plan = Plan(wl.params(), "c64")
+    a0, b0 = inputs(wl)
+    ae, be = torch.from_numpy(a0).cuda(), torch.from_numpy(b0).cuda()
+    pe = plan.propagate(ae, be)
+    torch.cuda.synchronize()
+    a, b = torch.from_numpy(a0).cuda(), torch.from_numpy(b0).cuda()
+    pw = torch.empty(2, dtype=torch.float64, device="cuda")
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.propagate(a, b, powers=pw)
+    for rep in range(3):
+        a.copy_(torch.from_numpy(a0).cuda())
+        b.copy_(torch.from_numpy(b0).cuda())
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(a, ae) and torch.equal(b, be) and torch.equal(pw, pe), rep
