@@ -9,10 +9,14 @@ from the seeded input field that is resident in HBM.
 
 Printed JSON line:
   value        cell-steps/s = nx * ny * nz * steps / wall time of the timed steps
-  roofline     dominant kernel (per-launch HIP events, timing mode): algorithmic
-               bytes per launch (both complex64 fields read and written once,
-               32 B per cell) / average launch duration, against 8 TB/s
-  cpu_baseline the FP64 oracle on a bounded sample of the same workload
+  roofline     dominant kernel: algorithmic bytes per launch (both complex64
+               fields read and written once, 32 B per cell) / its average launch
+               duration in the timed march (the timed region per step, split
+               between the row and column launches in the ratio of their
+               kernel durations, which timing mode measures with a HIP event
+               pair around every launch), against 8 TB/s
+  cpu_baseline the FP64 oracle on a bounded sample of the same workload, one
+               process per host core (and one process alone), with the CPU model
   extras       batched and forward+adjoint throughput when those paths run
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2]
@@ -63,22 +67,76 @@ def measured_traffic(kernel: str, launch_bytes: float):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
+# One oracle process of the CPU baseline: marches the first `steps` z-steps of
+# the benchmark workload and prints the seconds it took (the import and input
+# set-up are not timed).
+_ORACLE_SAMPLE = """
+import sys, time
+sys.path.insert(0, {root!r})
+import numpy as np
+import workloads
+from oracle import beams, ssfm
+wl = workloads.c2_plain_c64()
+p = wl.params()
+a0 = beams.input_pump(p, wl.power, wl.w0, wl.focus, workloads.phase_noise(wl)).astype(np.complex64)
+b0 = np.zeros_like(a0)
+t = time.perf_counter()
+ssfm.propagate(p, a0, b0, s_end={steps})
+print(time.perf_counter() - t)
+"""
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores() -> int:
+    """Cores this process may run on, capped at the 16 a one-GPU share holds."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def cpu_baseline(wl, sample_steps: int):
-    """Time the FP64 oracle (as it stands) on the first `sample_steps` z-steps."""
-    import numpy as np
-    import workloads
-    from oracle import beams, ssfm
-    p = dict(wl.params())
-    p["nz"] = wl.nz
-    a0 = beams.input_pump(p, wl.power, wl.w0, wl.focus, workloads.phase_noise(wl))
-    a0 = a0.astype(np.complex64)
-    b0 = np.zeros_like(a0)
-    t = time.perf_counter()
-    ssfm.propagate(p, a0, b0, s_end=sample_steps)
-    dt = time.perf_counter() - t
-    return {"value": wl.nx * wl.ny * sample_steps / dt, "unit": "cell-steps/s", "cores": 1,
+    """Time the FP64 oracle (as it stands) on the first `sample_steps` z-steps
+    of the workload: one process on one core, then one independent copy per
+    host core at once (the oracle's FFTs and pointwise steps are single
+    threaded, so independent marches are how it uses more cores).  Each copy
+    is a child Python process that touches no GPU."""
+    import subprocess
+    code = _ORACLE_SAMPLE.format(root=ROOT, steps=sample_steps)
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+
+    def run(n):
+        procs = [subprocess.Popen([sys.executable, "-c", code], stdout=subprocess.PIPE, env=env,
+                                  text=True) for _ in range(n)]
+        secs = []
+        for pr in procs:
+            out, _ = pr.communicate()
+            if pr.returncode != 0:
+                raise RuntimeError(f"oracle sample process failed ({pr.returncode})")
+            secs.append(float(out.strip().splitlines()[-1]))
+        return secs
+
+    cells = wl.nx * wl.ny * sample_steps
+    one = run(1)[0]
+    cores = host_cores()
+    many = run(cores)
+    return {"value": round(cells * cores / max(many), 1), "unit": "cell-steps/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{wl.name}: first {sample_steps} of {wl.nz} z-steps, numpy FP64, one thread"}
+            "sample": (f"{wl.name}: first {sample_steps} of {wl.nz} z-steps per process, numpy "
+                       f"FP64; {cores} independent processes at once (value: total cell-steps / "
+                       f"slowest process)"),
+            "single_core": {"value": round(cells / one, 1), "cores": 1, "seconds": round(one, 3)},
+            "cpu_model": cpu_model(), "host_cpus_visible": os.cpu_count()}
 
 
 def main(argv=None):
@@ -91,7 +149,8 @@ def main(argv=None):
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="",
                     help="comma-separated extra lines to run (default: all of "
-                         "batched, fwd_adj, thermal_fwd_adj, lnl, thermal, self_consistent)")
+                         "batched, fwd_adj, c5_forward, c1_complex128, thermal_fwd_adj, lnl, thermal, "
+                         "self_consistent)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 64 MiB device copy from a cache-cold source "
                          "(reference for the HBM byte counters)")
@@ -152,9 +211,9 @@ def main(argv=None):
     ms_per_step = ms / args.steps
     value = wl.cell_steps * args.steps / (ms / 1e3)
 
-    # per-kernel durations of the same march (timing mode: same kernels, one
-    # event pair around each launch); one march first, discarded, while the
-    # event pool fills and the launches settle
+    # per-kernel durations: timing mode brackets every launch of the same
+    # march (same kernels and arguments, no graph) with a HIP event pair on
+    # this stream; one march first, discarded, while the event pool fills
     plan.set_timing(True)
     step()
     plan.kernel_times()
@@ -162,9 +221,18 @@ def main(argv=None):
         step()
     kt = plan.kernel_times()
     plan.set_timing(False)
-    row_avg = kt["row_ms"] / max(1, kt["row_n"])
-    col_avg = kt["col_ms"] / max(1, kt["col_n"])
-    dom, avg_ms = ("row_pass", row_avg) if kt["row_ms"] >= kt["col_ms"] else ("col_pass", col_avg)
+    row_k = kt["row_ms"] / max(1, kt["row_n"])
+    col_k = kt["col_ms"] / max(1, kt["col_n"])
+    # the graph-replayed march runs one row and one column launch per z-step
+    # (plus one row launch): its per-launch time is the timed region per step,
+    # split between the two kernels in the ratio of their kernel durations
+    # (the two input copies, the phase table and the power reduction, about
+    # 0.2 % of a march, are charged to the passes)
+    launches = wl.nz + 1
+    ratio = row_k / col_k
+    col_avg = ms_per_step / (ratio * launches + wl.nz)
+    row_avg = ratio * col_avg
+    dom, avg_ms = ("row_pass", row_avg) if row_avg * launches >= col_avg * wl.nz else ("col_pass", col_avg)
     launch_bytes = 32.0 * wl.nx * wl.ny
     achieved = launch_bytes / (avg_ms * 1e-3) / 1e9
     traffic = measured_traffic(dom, launch_bytes)
@@ -173,6 +241,10 @@ def main(argv=None):
                 "traffic": traffic, "kernel": dom, "avg_launch_us": round(avg_ms * 1e3, 3),
                 "algorithmic_bytes_per_launch": int(launch_bytes),
                 "row_pass_avg_us": round(row_avg * 1e3, 3), "col_pass_avg_us": round(col_avg * 1e3, 3),
+                "launch_timing": ("timed graph-replayed march per step, split between the row and "
+                                  "column launches in the ratio of their event-bracketed kernel "
+                                  "durations"),
+                "row_pass_kernel_us": round(row_k * 1e3, 3), "col_pass_kernel_us": round(col_k * 1e3, 3),
                 "whole_march_frac_at_64B": round(value * 64.0 / (HBM_PEAK_GBS * 1e9), 4),
                 "whole_march_frac_at_32B": round(value * 32.0 / (HBM_PEAK_GBS * 1e9), 4)}
 

@@ -1,6 +1,7 @@
 """Secondary benchmark lines reported beside the single-instance forward march:
 the batched sweep (512 instances, sizes 64/128/256 in 1:2:1, nz in [200, 1000]),
-forward + adjoint on the 256 x 256 x 1000 differentiation workload, the heat
+forward + adjoint on the 256 x 256 x 1000 differentiation workload, the
+512 x 512 x 2000 temperature-field march, the 64 x 64 x 200 complex128 march, the heat
 equation for the heat of the 256 x 256 x 1000 march, and the self-consistent
 field <-> temperature loop of the 50 W workload (512 x 512 x 2000)."""
 from __future__ import annotations
@@ -55,6 +56,77 @@ def batched(device, reps=3, split="NLN"):
             "frac_hbm_at_64B": round(cells / sec * 64 / 8e12, 4)}
 
 
+def adjoint_bytes_per_cell_step(nz: int, k: int) -> float:
+    """Algorithmic HBM bytes per cell-step of a complex64 forward + adjoint with
+    checkpoints every k steps: forward 64 (two passes reading and writing both
+    fields), staged state written once per step 16, the recomputed fraction of
+    the forward 64 (every segment but the last, which the forward sweep stages
+    itself), adjoint row pass (cotangent in and out 32, staged state in 16) and
+    adjoint column pass 32, and a checkpoint of both fields per segment."""
+    segs = -(-nz // k)
+    last = nz - (segs - 1) * k
+    recomputed = (nz - last) / nz
+    return 64 + 16 + 64 * recomputed + 48 + 32 + 16 * segs / nz
+
+
+def c5_forward(device, reps=3):
+    """The 512 x 512 x 2000 temperature-field march (forward only): reported at
+    the 68 B/cell-step convention (64 B of fields plus one 4 B read of T per
+    step) and at the bytes this implementation moves (each T plane is read by
+    the two row passes around its step, 8 B, and the per-cell phase Psi is read
+    and written once per step, 8 B: 80 B)."""
+    import torch
+    import workloads
+    from paper_2410_04994_amd import Plan, beams, autotune
+    wl = workloads.c5_thermal_c64()
+    plan = Plan(wl.params(), "c64")
+    autotune.tune_single(plan)
+    temp = torch.from_numpy(workloads.RadialTemperature(wl, "float32").materialise()).to(device)
+    a_in = beams.pump_for(wl, dtype=torch.complex64, device=device)
+    a = torch.empty_like(a_in)
+    b = torch.zeros_like(a_in)
+    ws = plan.workspace(device=device)
+    pw = torch.empty(2, dtype=torch.float64, device=device)
+
+    def run():
+        a.copy_(a_in)
+        b.zero_()
+        plan.propagate(a, b, temp=temp, workspace=ws, powers=pw)
+
+    run()
+    sec = _timed(run, reps, torch)
+    rate = wl.cell_steps / sec
+    return {"workload": wl.name, "schedule": plan.describe(), "ms": round(sec * 1e3, 3),
+            "cell_steps_per_s": round(rate, 1), "frac_hbm_at_68B": round(rate * 68 / 8e12, 4),
+            "frac_hbm_at_80B": round(rate * 80 / 8e12, 4)}
+
+
+def c1_complex128(device, reps=20):
+    """The 64 x 64 x 200 lossless march in complex128 (FP64 arithmetic),
+    reported at 128 B/cell-step (the 64 B convention with 16-byte values)."""
+    import torch
+    import workloads
+    from paper_2410_04994_amd import Plan, beams
+    wl = workloads.c1_plain_fp64()
+    plan = Plan(wl.params(), "c128")
+    a_in = beams.pump_for(wl, dtype=torch.complex128, device=device)
+    a = torch.empty_like(a_in)
+    b = torch.zeros_like(a_in)
+    ws = plan.workspace(device=device)
+    pw = torch.empty(2, dtype=torch.float64, device=device)
+
+    def run():
+        a.copy_(a_in)
+        b.zero_()
+        plan.propagate(a, b, workspace=ws, powers=pw)
+
+    run()
+    sec = _timed(run, reps, torch)
+    rate = wl.cell_steps / sec
+    return {"workload": wl.name, "schedule": plan.describe(), "ms": round(sec * 1e3, 4),
+            "cell_steps_per_s": round(rate, 1), "frac_hbm_at_128B": round(rate * 128 / 8e12, 5)}
+
+
 def fwd_adj(device, reps=2):
     import torch
     import workloads
@@ -76,9 +148,13 @@ def fwd_adj(device, reps=2):
 
     run()
     sec = _timed(run, reps, torch)
+    k = int(plan.describe().split(" K=")[1].split(")")[0])
+    nbytes = adjoint_bytes_per_cell_step(wl.nz, k)
     out = {"workload": wl.name, "schedule": plan.describe(), "workspace_MB": round(ws.numel() / 2**20, 1),
            "cell_steps": wl.cell_steps, "ms_per_fwd_adj": round(sec * 1e3, 3),
            "cell_steps_per_s": round(wl.cell_steps / sec, 1),
+           "bytes_per_cell_step": round(nbytes, 2),
+           "frac_hbm": round(wl.cell_steps / sec * nbytes / 8e12, 4),
            "frac_hbm_at_224B": round(wl.cell_steps / sec * 224 / 8e12, 4)}
     # checkpoints every 32 steps, each segment recomputed in the reverse sweep
     plan32 = Plan(wl.params(), "c64", checkpoint_every=32)
@@ -90,9 +166,12 @@ def fwd_adj(device, reps=2):
 
     run32()
     sec32 = _timed(run32, reps, torch)
+    nb32 = adjoint_bytes_per_cell_step(wl.nz, 32)
     out["k32"] = {"schedule": plan32.describe(), "workspace_MB": round(ws32.numel() / 2**20, 1),
                   "ms_per_fwd_adj": round(sec32 * 1e3, 3),
                   "cell_steps_per_s": round(wl.cell_steps / sec32, 1),
+                  "bytes_per_cell_step": round(nb32, 2),
+                  "frac_hbm": round(wl.cell_steps / sec32 * nb32 / 8e12, 4),
                   "frac_hbm_at_224B": round(wl.cell_steps / sec32 * 224 / 8e12, 4)}
     return out
 
@@ -297,7 +376,8 @@ def lnl(device, steps=5):
 
 def run_all(device, only=None) -> dict:
     """Every extra line, or those named in `only`."""
-    lines = (("batched", batched), ("fwd_adj", fwd_adj), ("thermal_fwd_adj", thermal_fwd_adj),
+    lines = (("batched", batched), ("fwd_adj", fwd_adj), ("c5_forward", c5_forward),
+             ("c1_complex128", c1_complex128), ("thermal_fwd_adj", thermal_fwd_adj),
              ("lnl", lnl), ("thermal", thermal), ("self_consistent", self_consistent_loop))
     known = [name for name, _ in lines]
     unknown = [x for x in (only or []) if x not in known]
