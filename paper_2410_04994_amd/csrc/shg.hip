@@ -381,9 +381,10 @@ static constexpr double kC = 299792458.0;
 // Default adjoint checkpoint interval K.  The adjoint keeps ceil(nz/K) + 1
 // checkpoints and stages K steps (both fields plus the temperature phase Psi,
 // 5 reals per cell); the last segment is staged by the forward sweep itself, so
-// only the first nz - K steps are recomputed.  K = nz (nothing recomputed) when
-// that fits in kAdjointStateBudget, else the largest K whose checkpoints and
-// staging fit, but at least ceil(sqrt(nz)).
+// only the first nz - K steps are recomputed, and with recomputed segments the
+// staging is double-buffered (2K steps).  K = nz (nothing recomputed) when that
+// fits in kAdjointStateBudget, else the largest K whose checkpoints and staging
+// fit, but at least ceil(sqrt(nz)).
 static constexpr size_t kAdjointStateBudget = size_t(16) << 30;
 
 static int auto_checkpoint(int nz, size_t cells, int real_bytes) {
@@ -394,7 +395,7 @@ static int auto_checkpoint(int nz, size_t cells, int real_bytes) {
   while ((size_t)k_min * k_min < (size_t)nz) ++k_min;
   for (int k = nz; k > k_min; --k) {
     const size_t segs = ((size_t)nz + k - 1) / k;
-    if ((size_t)k + segs + 1 <= slots) return k;
+    if (2 * (size_t)k + segs + 1 <= slots) return k;
   }
   return k_min;
 }
