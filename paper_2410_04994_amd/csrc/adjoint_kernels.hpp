@@ -491,7 +491,7 @@ __global__ void __launch_bounds__(WideShape<N>::threads) row_adj_pass_wide(RowAd
   const int blk = blockIdx.x;
   const int tid = threadIdx.x;
   const bool fth = tid < S::fft_threads;
-  const int tr = fth ? tid / G : 0;
+  const int tr = transform_index<G>(fth, tid);
   const int t = tid % G;
   const int ff = tr & 1, fr = tr >> 1;
   const size_t frow = (size_t)(blk * ROWS + fr) * N;
@@ -506,7 +506,7 @@ __global__ void __launch_bounds__(WideShape<N>::threads) row_adj_pass_wide(RowAd
   const AdjPre<R, TH> pre = adj_load<R, TH>(p, q, idx, n2);
   if (p.inv_in) {
     if (fth) {
-      const auto src = gp(ff ? p.lb : p.la);
+      const auto src = gp(pick_ptr(ff, p.la, p.lb));
 #pragma unroll
       for (int m = 0; m < EF; ++m) v[m] = gload(src + (frow + t + G * m));
     }
@@ -535,7 +535,7 @@ __global__ void __launch_bounds__(WideShape<N>::threads) row_adj_pass_wide(RowAd
     }
     fft_pre<R, N, G, false, 1, (G <= 64)>(v, q0, q1, t, twr, fth);
     if (fth) {
-      const auto dst = gp(ff ? p.lb : p.la);
+      const auto dst = gp(pick_ptr(ff, p.la, p.lb));
 #pragma unroll
       for (int m = 0; m < EF; ++m) gstore(dst + (frow + t + G * m), v[m]);
     }

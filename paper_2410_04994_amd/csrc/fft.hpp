@@ -347,6 +347,28 @@ __device__ __forceinline__ void gstore(gmem<T>* q, T x) {
   *reinterpret_cast<gmem<V>*>(q) = __builtin_bit_cast(V, x);
 }
 
+// One of two pointers by a per-lane flag f (0 or 1), formed arithmetically
+// from their (uniform) values.  Written as a select of two adjacent kernel
+// arguments, the choice becomes a per-lane load from the argument segment: a
+// dependent memory round trip ahead of the loads that use the pointer.  The
+// empty asm hides f's range so that the arithmetic is not turned back into a
+// select.
+template <typename T>
+__device__ __forceinline__ T* pick_ptr(int f, T* p0, T* p1) {
+  asm volatile("" : "+v"(f));
+  const uintptr_t a = (uintptr_t)p0, b = (uintptr_t)p1;
+  return (T*)(a + (uintptr_t)(unsigned)f * (b - a));
+}
+
+// Index of the transform a thread works on: G threads per transform, so with
+// G >= 64 the index is uniform over each wavefront and is read as a scalar.
+template <int G>
+__device__ __forceinline__ int transform_index(bool active, int tid) {
+  const int tr = active ? tid / G : 0;
+  if constexpr (G >= 64) return __builtin_amdgcn_readfirstlane(tr);
+  return tr;
+}
+
 template <typename R, int N, int G, int NS, int REM>
 __device__ __forceinline__ void tw_gather(Tw<R>* out, int t, const gmem<Tw<R>>* __restrict__ tw) {
   if constexpr (REM > 1) {

@@ -436,7 +436,7 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
   const int tid = threadIdx.x;
   // transform role: transform tr = 2 * row + field, element t + G*m
   const bool fth = tid < S::fft_threads;
-  const int tr = fth ? tid / G : 0;
+  const int tr = transform_index<G>(fth, tid);
   const int t = tid % G;
   const int ff = tr & 1, fr = tr >> 1;
   const size_t frow = (size_t)(blk * ROWS + fr) * N;
@@ -481,7 +481,7 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
   }
   if (p.inv_in) {
     if (fth) {
-      const auto src = gp(ff ? p.bin : p.ain);
+      const auto src = gp(pick_ptr(ff, p.ain, p.bin));
 #pragma unroll
       for (int m = 0; m < EF; ++m) v[m] = gload(src + (frow + t + G * m));
     }
@@ -525,7 +525,7 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
     }
     fft_pre<R, N, G, false, 1, (G <= 64)>(v, q0, q1, t, twr, fth);
     if (fth) {
-      const auto dst = gp(ff ? p.bout : p.aout);
+      const auto dst = gp(pick_ptr(ff, p.aout, p.bout));
 #pragma unroll
       for (int m = 0; m < EF; ++m) gstore(dst + (frow + t + G * m), v[m]);
     }
