@@ -312,7 +312,7 @@ struct RowAdjTArgs {
 template <typename R, bool TH>
 struct AdjPre {
   cx<R> ua, ub;
-  HalfStep<R> c1, c2;
+  HalfStepPhase<R> e1, e2;   // table values; the coefficients are formed at use
   R psi, dT2, dT1;
   Carry<R> cr;
 };
@@ -324,8 +324,10 @@ __device__ __forceinline__ AdjPre<R, TH> adj_load(const RowAdjArgs<R>& p, const 
   a.ua = p.ua[idx];
   a.ub = p.ub[idx];
   if constexpr (!TH) {
-    if (p.s_first >= 0) a.c1 = half_step_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, p.full ? 2 : 1);
-    if (p.s_second >= 0) a.c2 = half_step_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks);
+    // unconditional (a step index < 0 reads step 0, unused): no wait on these
+    // loads stands before the cotangent loads that follow
+    a.e1 = half_step_phase<R>(gp(p.phase) + 5 * max(p.s_first, 0), p.full ? 2 : 1);
+    a.e2 = half_step_phase<R>(gp(p.phase) + 5 * max(p.s_second, 0) + 2);
   } else {
     a.psi = q.psi[idx];
     a.cr = q.carry[idx];
@@ -345,8 +347,8 @@ __device__ __forceinline__ void adj_cell(const RowAdjArgs<R>& p, const RowAdjTAr
   const cx<R> ub = pre.ub;
   cx<R> ya = ua, yb = ub;
   if constexpr (!TH) {
-    const HalfStep<R>& c1 = pre.c1;
-    const HalfStep<R>& c2 = pre.c2;
+    const HalfStep<R> c1 = coefs_of(pre.e1, p.kf, p.ks);
+    const HalfStep<R> c2 = coefs_of(pre.e2, p.kf, p.ks);
     if (p.s_second >= 0) rk4_cell(ya, yb, c2, p.tf, p.ts, h, und);
     R g = 0, gt = 0;
     if (p.s_first >= 0) {

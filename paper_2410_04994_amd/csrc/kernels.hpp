@@ -44,6 +44,31 @@ struct HalfStep {
 // e = exp(-i phi): cf = i kappa_F e, cs = i kappa_SH conj(e).  The stage
 // points are e[0], e[stride], e[2 stride] of the step's 5-point table: stride 1
 // for a half-step, 2 for a full step (L/2 - N - L/2 order).
+// The table values themselves: loaded early, turned into coefficients late.
+template <typename R>
+struct HalfStepPhase {
+  cx<R> e[3];
+};
+
+template <typename R, typename P>
+__device__ __forceinline__ HalfStepPhase<R> half_step_phase(P __restrict__ e, int stride = 1) {
+  HalfStepPhase<R> h;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) h.e[k] = gload(e + k * stride);
+  return h;
+}
+
+template <typename R>
+__device__ __forceinline__ HalfStep<R> coefs_of(const HalfStepPhase<R>& ph, R kf, R ks) {
+  HalfStep<R> h;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    h.cf[k] = {-kf * ph.e[k].im, kf * ph.e[k].re};
+    h.cs[k] = {ks * ph.e[k].im, ks * ph.e[k].re};
+  }
+  return h;
+}
+
 template <typename R, typename P>
 __device__ __forceinline__ HalfStep<R> half_step_coefs(P __restrict__ e, R kf, R ks,
                                                        int stride = 1) {
@@ -475,9 +500,14 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
                           p.lens_f, p.lens_sh, stf);
       if (p.full) psi2 += dkc * p.dz;
     }
-  } else {
-    if (p.s_second >= 0) c2 = half_step_coefs(gp(p.phase) + 5 * p.s_second + 2, p.kf, p.ks);
-    if (p.s_first >= 0) c1 = half_step_coefs(gp(p.phase) + 5 * p.s_first, p.kf, p.ks, stf);
+  }
+  // uniform mismatch: the table values are loaded here, unconditionally (a
+  // step index < 0 reads step 0, unused), and turned into coefficients after
+  // the transform, so that no wait on them stands before the field loads
+  HalfStepPhase<R> ph2{}, ph1{};
+  if constexpr (!TH) {
+    ph2 = half_step_phase<R>(gp(p.phase) + 5 * max(p.s_second, 0) + 2);
+    ph1 = half_step_phase<R>(gp(p.phase) + 5 * max(p.s_first, 0), stf);
   }
   if (p.inv_in) {
     if (fth) {
@@ -502,6 +532,10 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
     gstore(gp(p.tap_b) + idx, b);
   }
   const bool und = p.undepleted != 0;
+  if constexpr (!TH) {
+    c2 = coefs_of(ph2, p.kf, p.ks);
+    c1 = coefs_of(ph1, p.kf, p.ks);
+  }
   if constexpr (TH) {
     if (p.tap_psi) p.tap_psi[idx] = psi0;
     if (p.s_second >= 0) rk4_cell_t(a, b, c2t, p.tf, p.ts, p.h, und);
