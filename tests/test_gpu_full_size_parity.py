@@ -109,3 +109,35 @@ def test_differentiation_workload_full_size_against_oracle_adjoint_and_differenc
     assert e_f <= TOL_GRAD_C64 and e_th <= TOL_GRAD_C64 and e_dk <= TOL_GRAD_C64
     assert e_p <= TOL_ETA_C64
     assert e_fd <= TOL_GRAD_C64
+
+
+def test_temperature_field_workload_full_size_adjoint_against_oracle():
+    """512 x 512 x 2000 with the temperature field, loss P_SH(L): the complex64
+    adjoint (automatic checkpoint interval) gives the temperature moments
+    sum dP/dT (T - T_ref) and sum dP/dT (the gradients in the dT scale and in
+    T0) and the per-step mismatch gradient; all against the oracle's
+    reverse-mode gradient of the same march."""
+    from paper_2410_04994_amd import Plan, autotune
+    ref = golden("c5_adjoint")
+    wl = workloads.c5_thermal_c64()
+    print(f"case: {wl.name} adjoint against the oracle", flush=True)
+    a0, b0 = inputs(wl)
+    same_inputs(a0, ref["input"])
+    temp = torch.from_numpy(workloads.RadialTemperature(wl, np.float32).materialise()).cuda()
+    plan = Plan(wl.params(), "c64")
+    autotune.tune_single(plan)
+    w = torch.tensor([0.0, 1.0], dtype=torch.float64, device="cuda")
+    res = plan.adjoint(torch.from_numpy(a0).cuda(), torch.from_numpy(b0).cuda(), power_weights=w,
+                       temp=temp, want_dk=True, want_t=True)
+    torch.cuda.synchronize()
+    del temp
+    gm = res["g_t_moments"].cpu().numpy()
+    g_dk = res["g_dk"].cpu().numpy()
+    p_sh = float(res["powers"][1])
+    e_m = np.abs(gm / ref["g_t_moments"] - 1)
+    e_dk = rel(g_dk, ref["g_dk"])
+    e_p = abs(p_sh / ref["powers"][1] - 1)
+    print(f"{plan.describe()}: moments {gm} vs {ref['g_t_moments']} (rel {e_m}), g_dk={e_dk:.2e} "
+          f"P_SH={e_p:.2e}", flush=True)
+    assert np.all(e_m <= TOL_GRAD_C64) and e_dk <= TOL_GRAD_C64
+    assert e_p <= TOL_ETA_C64
