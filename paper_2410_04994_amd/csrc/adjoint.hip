@@ -13,6 +13,7 @@
 // and leave the cotangent of the segment's start state in real space.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -161,14 +162,20 @@ size_t adjoint_ws_bytes(const Plan& pl) { return adj_layout(pl).total; }
 struct AdjCache {
   hipStream_t side = nullptr, cap = nullptr;
   hipEvent_t fork = nullptr, join = nullptr, rec[2] = {}, used[2] = {};
-  hipGraphExec_t exec = nullptr;
-  std::vector<const void*> key;
+  // cached graphs, most recently used first (a few, for callers that cycle
+  // through a few output buffers)
+  static constexpr int kGraphs = 4;
+  struct Entry {
+    std::vector<const void*> key;
+    hipGraphExec_t exec;
+  };
+  std::vector<Entry> graphs;
 };
 
 void free_adjoint(Plan& pl) {
   AdjCache* c = (AdjCache*)pl.adj;
   if (!c) return;
-  if (c->exec) (void)hipGraphExecDestroy(c->exec);
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
   if (c->side) (void)hipStreamDestroy(c->side);
   if (c->cap) (void)hipStreamDestroy(c->cap);
   hipEvent_t evs[] = {c->fork, c->join, c->rec[0], c->rec[1], c->used[0], c->used[1]};
@@ -519,10 +526,9 @@ int propagate_adjoint(Plan& pl, const void* a_f_in, const void* a_sh_in, const d
         reinterpret_cast<const void*>((uintptr_t)(pl.row_e * 1000 + pl.row_wg)),
         reinterpret_cast<const void*>((uintptr_t)(pl.adj_e * 1000 + pl.adj_wg)),
         reinterpret_cast<const void*>((uintptr_t)(pl.col_e * 1000 + pl.col_tc))};
-    if (!ac->exec || ac->key != key) {
-      if (ac->exec) (void)hipGraphExecDestroy(ac->exec);
-      ac->exec = nullptr;
-      ac->key.clear();
+    size_t hit = 0;
+    while (hit < ac->graphs.size() && ac->graphs[hit].key != key) ++hit;
+    if (hit == ac->graphs.size()) {
       if (!ac->cap) {
         e = hipStreamCreateWithFlags(&ac->cap, hipStreamNonBlocking);
         if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
@@ -537,15 +543,19 @@ int propagate_adjoint(Plan& pl, const void* a_f_in, const void* a_sh_in, const d
         return rc;
       }
       if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
-      e = hipGraphInstantiate(&ac->exec, g, nullptr, nullptr, 0);
+      hipGraphExec_t exec = nullptr;
+      e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
-      if (e != hipSuccess) {
-        ac->exec = nullptr;
-        return hip_fail(e, "hipGraphInstantiate");
+      if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+      if ((int)ac->graphs.size() == AdjCache::kGraphs) {
+        (void)hipGraphExecDestroy(ac->graphs.back().exec);
+        ac->graphs.pop_back();
       }
-      ac->key = key;
+      ac->graphs.insert(ac->graphs.begin(), AdjCache::Entry{key, exec});
+    } else if (hit > 0) {
+      std::rotate(ac->graphs.begin(), ac->graphs.begin() + hit, ac->graphs.begin() + hit + 1);
     }
-    e = hipGraphLaunch(ac->exec, st);
+    e = hipGraphLaunch(ac->graphs.front().exec, st);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   }
   if (rc || !checks_finite(pl)) return rc;

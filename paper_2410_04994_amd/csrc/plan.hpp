@@ -63,8 +63,15 @@ struct Plan {
   // cached forward graph
   hipStream_t cap_stream = nullptr;
   int* finite_flag = nullptr;  // device int of the SHG_CHECK_FINITE scans (plans with the flag)
-  hipGraphExec_t gexec = nullptr;
-  GraphKey gkey{};
+  // cached graphs of the march, most recently used first; a few entries, so
+  // that callers cycling through a few buffers (e.g. fresh output tensors from
+  // an allocator) replay instead of capturing again
+  static constexpr int kGraphCache = 4;
+  struct CachedGraph {
+    GraphKey key;
+    hipGraphExec_t exec;
+  };
+  std::vector<CachedGraph> graphs;
   // optional per-kernel timing (kind 0 = row pass, 1 = column pass)
   int timing = 0;
   std::vector<hipEvent_t> ev_pool;

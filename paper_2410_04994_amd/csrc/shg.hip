@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -476,8 +477,8 @@ void free_timing(Plan& pl) {
 
 void free_plan_tables(Plan& pl) {
   free_timing(pl);
-  if (pl.gexec) (void)hipGraphExecDestroy(pl.gexec);
-  pl.gexec = nullptr;
+  for (auto& g : pl.graphs) (void)hipGraphExecDestroy(g.exec);
+  pl.graphs.clear();
   if (pl.cap_stream) (void)hipStreamDestroy(pl.cap_stream);
   pl.cap_stream = nullptr;
   void* ptrs[] = {pl.tw_x, pl.tw_y, pl.mx[0], pl.mx[1], pl.my[0], pl.my[1], pl.mxh[0], pl.mxh[1],
@@ -734,11 +735,9 @@ static int run_forward(Plan& pl, void* a, void* b, const double* dk_z, const voi
   if (!use_graph) return enqueue_forward_temp(pl, a, b, dk_z, temp, s0, s1, ws, powers, st, heat);
   GraphKey key{a,  b,  dk_z, temp, heat, ws, powers, s0, s1, pl.row_e, pl.row_wg, pl.col_e,
                pl.col_tc};
-  if (!pl.gexec || !(key == pl.gkey)) {
-    if (pl.gexec) {
-      (void)hipGraphExecDestroy(pl.gexec);
-      pl.gexec = nullptr;
-    }
+  size_t hit = 0;
+  while (hit < pl.graphs.size() && !(pl.graphs[hit].key == key)) ++hit;
+  if (hit == pl.graphs.size()) {
     if (!pl.cap_stream) {
       e = hipStreamCreateWithFlags(&pl.cap_stream, hipStreamNonBlocking);
       if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
@@ -753,15 +752,19 @@ static int run_forward(Plan& pl, void* a, void* b, const double* dk_z, const voi
       return rc;
     }
     if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
-    e = hipGraphInstantiate(&pl.gexec, g, nullptr, nullptr, 0);
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-      pl.gexec = nullptr;
-      return hip_fail(e, "hipGraphInstantiate");
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    if ((int)pl.graphs.size() == Plan::kGraphCache) {
+      (void)hipGraphExecDestroy(pl.graphs.back().exec);
+      pl.graphs.pop_back();
     }
-    pl.gkey = key;
+    pl.graphs.insert(pl.graphs.begin(), Plan::CachedGraph{key, exec});
+  } else if (hit > 0) {
+    std::rotate(pl.graphs.begin(), pl.graphs.begin() + hit, pl.graphs.begin() + hit + 1);
   }
-  e = hipGraphLaunch(pl.gexec, st);
+  e = hipGraphLaunch(pl.graphs.front().exec, st);
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   return SHG_OK;
 }

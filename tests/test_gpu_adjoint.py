@@ -404,3 +404,26 @@ def test_overlapped_recompute_graph_equals_serial_launches(split, thermal):
         torch.cuda.synchronize()
         for k in ref:
             assert torch.equal(got[k], ref[k]), (rep, k)
+
+
+def test_adjoint_graph_cache_keeps_several_output_sets():
+    """Adjoint calls with two sets of output buffers, alternating, equal the
+    serial launches of an SHG_NO_GRAPH plan bit for bit."""
+    from paper_2410_04994_amd import Plan
+    from paper_2410_04994_amd.binding import SHG_NO_GRAPH
+    wl = small_case(n=32, nz=12)[0]
+    a0, b0 = inputs(wl, "c64")
+    a, b = cuda(a0), cuda(b0)
+    w = cuda(np.array([0.3, 1.0]))
+    ref = Plan(wl.params(), "c64", flags=SHG_NO_GRAPH, checkpoint_every=5).adjoint(
+        a, b, power_weights=w, want_dk=True)
+    torch.cuda.synchronize()
+    plan = Plan(wl.params(), "c64", checkpoint_every=5)
+    ws = plan.workspace(adjoint=True)
+    outs = [{k: torch.empty_like(v) for k, v in ref.items()} for _ in range(2)]
+    for rnd in range(3):
+        for out in outs:
+            got = plan.adjoint(a, b, power_weights=w, want_dk=True, workspace=ws, out=out)
+            torch.cuda.synchronize()
+            for k in ref:
+                assert torch.equal(got[k], ref[k]), (rnd, k)

@@ -491,3 +491,27 @@ def test_march_without_workspace_records_under_stream_capture():
         graph.replay()
         torch.cuda.synchronize()
         assert torch.equal(a, ae) and torch.equal(b, be) and torch.equal(pw, pe), rep
+
+
+def test_graph_cache_keeps_several_argument_sets():
+    """A plan keeps the graphs of its last few argument sets: marches on two
+    sets of buffers, called alternately (as with fresh output tensors from an
+    allocator), replay their own graphs and equal the one-by-one launches of
+    an SHG_NO_GRAPH plan bit for bit."""
+    from paper_2410_04994_amd import Plan
+    from paper_2410_04994_amd.binding import SHG_NO_GRAPH
+    wl = workloads.c2_plain_c64().with_(nx=64, ny=64, nz=20)
+    a0, b0 = inputs(wl)
+    ref = Plan(wl.params(), "c64", flags=SHG_NO_GRAPH)
+    ra, rb = torch.from_numpy(a0).cuda(), torch.from_numpy(b0).cuda()
+    rp = ref.propagate(ra, rb)
+    plan = Plan(wl.params(), "c64")
+    sets = [(torch.empty_like(ra), torch.empty_like(rb), torch.empty(2, dtype=torch.float64, device="cuda"))
+            for _ in range(2)]
+    for rnd in range(3):
+        for a, b, pw in sets:
+            a.copy_(torch.from_numpy(a0).cuda())
+            b.copy_(torch.from_numpy(b0).cuda())
+            plan.propagate(a, b, powers=pw)
+            torch.cuda.synchronize()
+            assert torch.equal(a, ra) and torch.equal(b, rb) and torch.equal(pw, rp), rnd
