@@ -365,23 +365,24 @@ __device__ __forceinline__ void adj_cell(const RowAdjArgs<R>& p, const RowAdjTAr
     }
   } else {
     const R qdz = q.dz * (R)0.25;
-    R psi = pre.psi;
+    // the forward pass's stage coefficients, formed the same way
+    cx<R> rho = expi_neg(pre.psi);
     Carry<R> cr = pre.cr;
     HalfStepT<R> c2{};
     if (p.s_second >= 0) {
       const R dT = pre.dT2;
-      const R dkc = thermal_dk(dT, q.dk);
-      c2 = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, psi, dkc, dT, h, qdz,
+      const cx<R> step = expi_neg_small(thermal_dk(dT, q.dk) * qdz), st2 = step * step;
+      c2 = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, rho * st2, step, dT,
                          q.lens_f, q.lens_sh);
       rk4_cell_t(ya, yb, c2, p.tf, p.ts, h, und);
-      psi += dkc * q.dz;
+      rho = rho * (st2 * st2);
     }
     if (p.s_first >= 0) {
       const R dT = pre.dT1;
       const int st = p.full ? 2 : 1;
-      const HalfStepT<R> c1 = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, psi,
-                                            thermal_dk(dT, q.dk), dT, (R)0, qdz * (R)st,
-                                            q.lens_f, q.lens_sh, st);
+      const HalfStepT<R> c1 =
+          thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, rho,
+                        expi_neg_small(thermal_dk(dT, q.dk) * (qdz * st)), dT, q.lens_f, q.lens_sh, st);
       R g = 0, gt = 0, gl = 0;
       rk4_vjp_t(ya, yb, la, lb, c1, p.tf, p.ts, q.lens_f, q.lens_sh, h * (R)st, und, (R)0, g, gt,
                 gl);

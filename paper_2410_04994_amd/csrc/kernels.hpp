@@ -147,30 +147,69 @@ inline DkT<R> make_dk_shift(double c1, double c2, double c3, double lam25, doubl
 
 template <typename R>
 __device__ __forceinline__ R thermal_dk(R dT, const DkT<R>& k) {
-  const R x = k.xr + dT;
-  const R u = (R)1 + x * (k.a + x * k.b);
-  return dT * (k.c1 + dT * (k.c2 + dT * k.c3)) + k.g * dT * (k.a + k.b * (k.xr + x)) / u;
+  R d = dT * (k.c1 + dT * (k.c2 + dT * k.c3));
+  if (k.g != (R)0) {
+    const R x = k.xr + dT;
+    const R u = (R)1 + x * (k.a + x * k.b);
+    d += k.g * dT * (k.a + k.b * (k.xr + x)) / u;
+  }
+  return d;
 }
 template <typename R>
 __device__ __forceinline__ R thermal_dk_slope(R dT, const DkT<R>& k) {
-  const R x = k.xr + dT;
-  const R u = (R)1 + x * (k.a + x * k.b);
-  return k.c1 + dT * ((R)2 * k.c2 + (R)3 * k.c3 * dT) + k.g25 * (k.a + (R)2 * k.b * x) / (u * u);
+  R d = k.c1 + dT * ((R)2 * k.c2 + (R)3 * k.c3 * dT);
+  if (k.g25 != (R)0) {
+    const R x = k.xr + dT;
+    const R u = (R)1 + x * (k.a + x * k.b);
+    d += k.g25 * (k.a + (R)2 * k.b * x) / (u * u);
+  }
+  return d;
 }
 
-// Stage coefficients at tau0, tau0 + qdz, tau0 + 2 qdz for one cell with
-// carried phase psi, mismatch shift dkc and lens sample dT (qdz = dz/4 and
-// stride 1 for a half-step; dz/2 and stride 2 for a full step).
+// exp(-i x)
+template <typename R>
+__device__ __forceinline__ cx<R> expi_neg(R x) {
+  R sn, c;
+  sincos_r(x, &sn, &c);
+  return {c, -sn};
+}
+
+// exp(-i x) for the phase advance of a quarter step, dkc dz/4, a small angle:
+// Taylor series of cos and sin when |x| <= 1/8 in float (first omitted term
+// below 6e-9) or 1/16 in double (below 3e-19), else sincos.
+template <typename R>
+__device__ __forceinline__ cx<R> expi_neg_small(R x) {
+  const R x2 = x * x;
+  if constexpr (sizeof(R) == 4) {
+    if (fabsf(x) <= 0.125f) {
+      const float c = 1.0f + x2 * (-0.5f + x2 * (1.0f / 24.0f));
+      const float sn = x * (1.0f + x2 * (-1.0f / 6.0f + x2 * (1.0f / 120.0f)));
+      return {c, -sn};
+    }
+  } else {
+    if (fabs(x) <= 0.0625) {
+      const double c = 1.0 + x2 * (-1.0 / 2 + x2 * (1.0 / 24 + x2 * (-1.0 / 720 + x2 * (1.0 / 40320))));
+      const double sn =
+          x * (1.0 + x2 * (-1.0 / 6 + x2 * (1.0 / 120 + x2 * (-1.0 / 5040 + x2 * (1.0 / 362880)))));
+      return {c, -sn};
+    }
+  }
+  return expi_neg(x);
+}
+
+// Stage coefficients of one cell's half-step (stride 1) or full step
+// (stride 2) with a temperature field: rho = exp(-i phase) at the first stage,
+// step = exp(-i dkc qdz) the advance from stage to stage (qdz = dz/4 for a
+// half-step, dz/2 for a full step) and dT the lens sample.  The phase at the
+// start of a step is the carried Psi of the cell, exp(-i Psi) is formed once
+// per pass, and the later stages and the next step's start follow by products
+// of step: the second half of a step starts at step^2, the next step at
+// step^4 of the start of this one.
 template <typename R>
 __device__ __forceinline__ HalfStepT<R> thermal_coefs(const cx<R>* __restrict__ e, R kf, R ks,
-                                                      R psi, R dkc, R dT, R tau0, R qdz,
-                                                      R lens_f, R lens_sh, int stride = 1) {
+                                                      cx<R> rho, cx<R> step, R dT, R lens_f,
+                                                      R lens_sh, int stride = 1) {
   HalfStepT<R> h;
-  R sn, c;
-  sincos_r(psi + dkc * tau0, &sn, &c);
-  cx<R> rho = {c, -sn};
-  sincos_r(dkc * qdz, &sn, &c);
-  const cx<R> step = {c, -sn};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const cx<R> ek = e[k * stride] * rho;
@@ -335,21 +374,25 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
       const size_t idx = row + t + G * m;
       R psi = p.psi[idx];
       if (p.tap_psi) p.tap_psi[idx] = psi;
+      cx<R> rho = expi_neg(psi);
       if (p.s_second >= 0) {
         const R dT = p.temp[(size_t)p.s_second * n2 + idx] - p.t_ref;
         const R dkc = thermal_dk(dT, p.dk);
-        const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, psi, dkc,
-                                             dT, p.h, qdz, p.lens_f, p.lens_sh);
+        const cx<R> step = expi_neg_small(dkc * qdz), st2 = step * step;
+        const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, rho * st2,
+                                             step, dT, p.lens_f, p.lens_sh);
         rk4_cell_t(va[m], vb[m], c, p.tf, p.ts, p.h, und);
         psi += dkc * p.dz;
+        rho = rho * (st2 * st2);
       }
       if (p.heat) p.heat[idx] = heat_density(va[m], vb[m], p);
       if (p.s_first >= 0) {
         const R dT = p.temp[(size_t)p.s_first * n2 + idx] - p.t_ref;
         const R dkc = thermal_dk(dT, p.dk);
         const int st = p.full ? 2 : 1;
-        const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, psi, dkc, dT,
-                                             (R)0, qdz * st, p.lens_f, p.lens_sh, st);
+        const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, rho,
+                                             expi_neg_small(dkc * (qdz * st)), dT, p.lens_f,
+                                             p.lens_sh, st);
         rk4_cell_t(va[m], vb[m], c, p.tf, p.ts, p.h * st, und);
         if (p.full) psi += dkc * p.dz;
       }
@@ -485,19 +528,22 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
     const R qdz = p.dz * (R)0.25;
     psi0 = p.psi[idx];
     psi1 = psi0;
+    cx<R> rho = expi_neg(psi0);
     if (p.s_second >= 0) {
       const R dT = p.temp[(size_t)p.s_second * n2 + idx] - p.t_ref;
       const R dkc = thermal_dk(dT, p.dk);
-      c2t = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, psi0, dkc, dT, p.h, qdz,
+      const cx<R> step = expi_neg_small(dkc * qdz), st2 = step * step;
+      c2t = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, rho * st2, step, dT,
                           p.lens_f, p.lens_sh);
       psi1 += dkc * p.dz;
+      rho = rho * (st2 * st2);
     }
     psi2 = psi1;
     if (p.s_first >= 0) {
       const R dT = p.temp[(size_t)p.s_first * n2 + idx] - p.t_ref;
       const R dkc = thermal_dk(dT, p.dk);
-      c1t = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, psi1, dkc, dT, (R)0, qdz * stf,
-                          p.lens_f, p.lens_sh, stf);
+      c1t = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, rho, expi_neg_small(dkc * (qdz * stf)),
+                          dT, p.lens_f, p.lens_sh, stf);
       if (p.full) psi2 += dkc * p.dz;
     }
   }
