@@ -313,27 +313,36 @@ template <typename R, bool TH>
 struct AdjPre {
   cx<R> ua, ub;
   HalfStepPhase<R> e1, e2;   // table values; the coefficients are formed at use
-  R psi, dT2, dT1;
+  R psi, t2, t1;             // Psi and the raw samples T of both steps
   Carry<R> cr;
 };
 
+// The table values (scalar loads), then the per-cell values (vector loads).
+// All unconditional (a step index < 0 reads step 0, unused) and raw, so that
+// no wait on them stands before the loads that follow them.
+template <typename R, bool TH>
+__device__ __forceinline__ void adj_load_table(const RowAdjArgs<R>& p, AdjPre<R, TH>& a) {
+  a.e1 = half_step_phase<R>(gp(p.phase) + 5 * max(p.s_first, 0), p.full ? 2 : 1);
+  a.e2 = half_step_phase<R>(gp(p.phase) + 5 * max(p.s_second, 0) + 2);
+}
+template <typename R, bool TH>
+__device__ __forceinline__ void adj_load_cell(const RowAdjArgs<R>& p, const RowAdjTArgs<R>& q,
+                                              size_t idx, size_t n2, AdjPre<R, TH>& a) {
+  a.ua = p.ua[idx];
+  a.ub = p.ub[idx];
+  if constexpr (TH) {
+    a.psi = q.psi[idx];
+    a.cr = q.carry[idx];
+    a.t2 = q.temp[(size_t)max(p.s_second, 0) * n2 + idx];
+    a.t1 = q.temp[(size_t)max(p.s_first, 0) * n2 + idx];
+  }
+}
 template <typename R, bool TH>
 __device__ __forceinline__ AdjPre<R, TH> adj_load(const RowAdjArgs<R>& p, const RowAdjTArgs<R>& q,
                                                   size_t idx, size_t n2) {
   AdjPre<R, TH> a{};
-  a.ua = p.ua[idx];
-  a.ub = p.ub[idx];
-  if constexpr (!TH) {
-    // unconditional (a step index < 0 reads step 0, unused): no wait on these
-    // loads stands before the cotangent loads that follow
-    a.e1 = half_step_phase<R>(gp(p.phase) + 5 * max(p.s_first, 0), p.full ? 2 : 1);
-    a.e2 = half_step_phase<R>(gp(p.phase) + 5 * max(p.s_second, 0) + 2);
-  } else {
-    a.psi = q.psi[idx];
-    a.cr = q.carry[idx];
-    if (p.s_second >= 0) a.dT2 = q.temp[(size_t)p.s_second * n2 + idx] - q.t_ref;
-    if (p.s_first >= 0) a.dT1 = q.temp[(size_t)p.s_first * n2 + idx] - q.t_ref;
-  }
+  adj_load_table<R, TH>(p, a);
+  adj_load_cell<R, TH>(p, q, idx, n2, a);
   return a;
 }
 
@@ -370,19 +379,18 @@ __device__ __forceinline__ void adj_cell(const RowAdjArgs<R>& p, const RowAdjTAr
     Carry<R> cr = pre.cr;
     HalfStepT<R> c2{};
     if (p.s_second >= 0) {
-      const R dT = pre.dT2;
+      const R dT = pre.t2 - q.t_ref;
       const cx<R> step = expi_neg_small(thermal_dk(dT, q.dk) * qdz), st2 = step * step;
-      c2 = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, rho * st2, step, dT,
-                         q.lens_f, q.lens_sh);
+      c2 = thermal_coefs(pre.e2, p.kf, p.ks, rho * st2, step, dT, q.lens_f, q.lens_sh);
       rk4_cell_t(ya, yb, c2, p.tf, p.ts, h, und);
       rho = rho * (st2 * st2);
     }
     if (p.s_first >= 0) {
-      const R dT = pre.dT1;
+      const R dT = pre.t1 - q.t_ref;
       const int st = p.full ? 2 : 1;
       const HalfStepT<R> c1 =
-          thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, rho,
-                        expi_neg_small(thermal_dk(dT, q.dk) * (qdz * st)), dT, q.lens_f, q.lens_sh, st);
+          thermal_coefs(pre.e1, p.kf, p.ks, rho, expi_neg_small(thermal_dk(dT, q.dk) * (qdz * st)),
+                        dT, q.lens_f, q.lens_sh);
       R g = 0, gt = 0, gl = 0;
       rk4_vjp_t(ya, yb, la, lb, c1, p.tf, p.ts, q.lens_f, q.lens_sh, h * (R)st, und, (R)0, g, gt,
                 gl);
@@ -506,13 +514,17 @@ __global__ void __launch_bounds__(WideShape<N>::threads) row_adj_pass_wide(RowAd
   cx<R> la, lb;
   TwRegs<R, N, G> twr;
   if (fth) tw_load(twr, t, p.tw);
-  const AdjPre<R, TH> pre = adj_load<R, TH>(p, q, idx, n2);
+  // the table values first; the per-cell inputs after the cotangent loads, so
+  // that the transform waits only for the cotangent and they arrive during it
+  AdjPre<R, TH> pre{};
+  adj_load_table<R, TH>(p, pre);
   if (p.inv_in) {
     if (fth) {
       const auto src = gp(pick_ptr(ff, p.la, p.lb));
 #pragma unroll
       for (int m = 0; m < EF; ++m) v[m] = gload(src + (frow + t + G * m));
     }
+    adj_load_cell<R, TH>(p, q, idx, n2, pre);
     fft_pre<R, N, G, true, 1, (G <= 64)>(v, q0, q1, t, twr, fth);
     if (fth) {
 #pragma unroll
@@ -524,6 +536,7 @@ __global__ void __launch_bounds__(WideShape<N>::threads) row_adj_pass_wide(RowAd
   } else {
     la = gload(gp(p.la) + idx);
     lb = gload(gp(p.lb) + idx);
+    adj_load_cell<R, TH>(p, q, idx, n2, pre);
   }
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   adj_cell<R, TH>(p, q, pre, idx, la, lb, acc);

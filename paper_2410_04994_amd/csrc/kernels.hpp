@@ -197,8 +197,9 @@ __device__ __forceinline__ cx<R> expi_neg_small(R x) {
   return expi_neg(x);
 }
 
-// Stage coefficients of one cell's half-step (stride 1) or full step
-// (stride 2) with a temperature field: rho = exp(-i phase) at the first stage,
+// Stage coefficients of one cell's half-step or full step with a temperature
+// field: ph the uniform table values at the three stage points, rho =
+// exp(-i phase) at the first stage,
 // step = exp(-i dkc qdz) the advance from stage to stage (qdz = dz/4 for a
 // half-step, dz/2 for a full step) and dT the lens sample.  The phase at the
 // start of a step is the carried Psi of the cell, exp(-i Psi) is formed once
@@ -206,13 +207,13 @@ __device__ __forceinline__ cx<R> expi_neg_small(R x) {
 // of step: the second half of a step starts at step^2, the next step at
 // step^4 of the start of this one.
 template <typename R>
-__device__ __forceinline__ HalfStepT<R> thermal_coefs(const cx<R>* __restrict__ e, R kf, R ks,
+__device__ __forceinline__ HalfStepT<R> thermal_coefs(const HalfStepPhase<R>& ph, R kf, R ks,
                                                       cx<R> rho, cx<R> step, R dT, R lens_f,
-                                                      R lens_sh, int stride = 1) {
+                                                      R lens_sh) {
   HalfStepT<R> h;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const cx<R> ek = e[k * stride] * rho;
+    const cx<R> ek = ph.e[k] * rho;
     h.cf[k] = {-kf * ek.im, kf * ek.re};
     h.cs[k] = {ks * ek.im, ks * ek.re};
     rho = rho * step;
@@ -379,8 +380,9 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
         const R dT = p.temp[(size_t)p.s_second * n2 + idx] - p.t_ref;
         const R dkc = thermal_dk(dT, p.dk);
         const cx<R> step = expi_neg_small(dkc * qdz), st2 = step * step;
-        const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, rho * st2,
-                                             step, dT, p.lens_f, p.lens_sh);
+        const HalfStepT<R> c =
+            thermal_coefs(half_step_phase<R>(p.phase + 5 * p.s_second + 2), p.kf, p.ks, rho * st2,
+                          step, dT, p.lens_f, p.lens_sh);
         rk4_cell_t(va[m], vb[m], c, p.tf, p.ts, p.h, und);
         psi += dkc * p.dz;
         rho = rho * (st2 * st2);
@@ -390,9 +392,9 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
         const R dT = p.temp[(size_t)p.s_first * n2 + idx] - p.t_ref;
         const R dkc = thermal_dk(dT, p.dk);
         const int st = p.full ? 2 : 1;
-        const HalfStepT<R> c = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, rho,
-                                             expi_neg_small(dkc * (qdz * st)), dT, p.lens_f,
-                                             p.lens_sh, st);
+        const HalfStepT<R> c =
+            thermal_coefs(half_step_phase<R>(p.phase + 5 * p.s_first, st), p.kf, p.ks, rho,
+                          expi_neg_small(dkc * (qdz * st)), dT, p.lens_f, p.lens_sh);
         rk4_cell_t(va[m], vb[m], c, p.tf, p.ts, p.h * st, und);
         if (p.full) psi += dkc * p.dz;
       }
@@ -516,51 +518,31 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
   cx<R> a, b;
   TwRegs<R, N, G> twr;
   if (fth) tw_load(twr, t, p.tw);
-  // stage coefficients of both half-steps (with a temperature field: of this
-  // cell, from its Psi and samples), formed before the transform so that the
-  // table and field reads overlap it
-  const int stf = p.full ? 2 : 1;
-  HalfStep<R> c2{}, c1{};
-  HalfStepT<R> c2t{}, c1t{};
-  R psi0 = (R)0, psi1 = (R)0, psi2 = (R)0;
-  if constexpr (TH) {
-    const size_t n2 = (size_t)p.ny * N;
-    const R qdz = p.dz * (R)0.25;
-    psi0 = p.psi[idx];
-    psi1 = psi0;
-    cx<R> rho = expi_neg(psi0);
-    if (p.s_second >= 0) {
-      const R dT = p.temp[(size_t)p.s_second * n2 + idx] - p.t_ref;
-      const R dkc = thermal_dk(dT, p.dk);
-      const cx<R> step = expi_neg_small(dkc * qdz), st2 = step * step;
-      c2t = thermal_coefs(p.phase + 5 * p.s_second + 2, p.kf, p.ks, rho * st2, step, dT,
-                          p.lens_f, p.lens_sh);
-      psi1 += dkc * p.dz;
-      rho = rho * (st2 * st2);
-    }
-    psi2 = psi1;
-    if (p.s_first >= 0) {
-      const R dT = p.temp[(size_t)p.s_first * n2 + idx] - p.t_ref;
-      const R dkc = thermal_dk(dT, p.dk);
-      c1t = thermal_coefs(p.phase + 5 * p.s_first, p.kf, p.ks, rho, expi_neg_small(dkc * (qdz * stf)),
-                          dT, p.lens_f, p.lens_sh, stf);
-      if (p.full) psi2 += dkc * p.dz;
-    }
-  }
-  // uniform mismatch: the table values are loaded here, unconditionally (a
+  // the table values of both half-steps are loaded here, unconditionally (a
   // step index < 0 reads step 0, unused), and turned into coefficients after
   // the transform, so that no wait on them stands before the field loads
-  HalfStepPhase<R> ph2{}, ph1{};
-  if constexpr (!TH) {
-    ph2 = half_step_phase<R>(gp(p.phase) + 5 * max(p.s_second, 0) + 2);
-    ph1 = half_step_phase<R>(gp(p.phase) + 5 * max(p.s_first, 0), stf);
-  }
+  const int stf = p.full ? 2 : 1;
+  const HalfStepPhase<R> ph2 = half_step_phase<R>(gp(p.phase) + 5 * max(p.s_second, 0) + 2);
+  const HalfStepPhase<R> ph1 = half_step_phase<R>(gp(p.phase) + 5 * max(p.s_first, 0), stf);
+  // with a temperature field: the cell's Psi and its two samples, raw, loaded
+  // after the field loads (unconditionally, like the table values), so that
+  // the transform waits only for the fields
+  R th_psi = (R)0, th_t2 = (R)0, th_t1 = (R)0;
+  const auto th_loads = [&]() {
+    if constexpr (TH) {
+      const size_t n2 = (size_t)p.ny * N;
+      th_psi = p.psi[idx];
+      th_t2 = p.temp[(size_t)max(p.s_second, 0) * n2 + idx];
+      th_t1 = p.temp[(size_t)max(p.s_first, 0) * n2 + idx];
+    }
+  };
   if (p.inv_in) {
     if (fth) {
       const auto src = gp(pick_ptr(ff, p.ain, p.bin));
 #pragma unroll
       for (int m = 0; m < EF; ++m) v[m] = gload(src + (frow + t + G * m));
     }
+    th_loads();
     fft_pre<R, N, G, true, 1, (G <= 64)>(v, q0, q1, t, twr, fth);
     if (fth) {
 #pragma unroll
@@ -572,23 +554,45 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
   } else {
     a = gload(gp(p.ain) + idx);
     b = gload(gp(p.bin) + idx);
+    th_loads();
   }
   if (p.tap_a) {
     gstore(gp(p.tap_a) + idx, a);
     gstore(gp(p.tap_b) + idx, b);
   }
   const bool und = p.undepleted != 0;
-  if constexpr (!TH) {
-    c2 = coefs_of(ph2, p.kf, p.ks);
-    c1 = coefs_of(ph1, p.kf, p.ks);
-  }
   if constexpr (TH) {
-    if (p.tap_psi) p.tap_psi[idx] = psi0;
-    if (p.s_second >= 0) rk4_cell_t(a, b, c2t, p.tf, p.ts, p.h, und);
+    // Psi of this cell, the phase rho = exp(-i Psi) and the stage
+    // coefficients of each half-step, formed just before its RK4
+    if (p.tap_psi) p.tap_psi[idx] = th_psi;
+    const R qdz = p.dz * (R)0.25;
+    R psi = th_psi;
+    cx<R> rho = expi_neg(psi);
+    if (p.s_second >= 0) {
+      const R dT = th_t2 - p.t_ref;
+      const R dkc = thermal_dk(dT, p.dk);
+      const cx<R> step = expi_neg_small(dkc * qdz), st2 = step * step;
+      const HalfStepT<R> c2t =
+          thermal_coefs(ph2, p.kf, p.ks, rho * st2, step, dT, p.lens_f, p.lens_sh);
+      rk4_cell_t(a, b, c2t, p.tf, p.ts, p.h, und);
+      psi += dkc * p.dz;
+      rho = rho * (st2 * st2);
+    }
     if (p.heat) p.heat[idx] = heat_density(a, b, p);
-    if (p.s_first >= 0) rk4_cell_t(a, b, c1t, p.tf, p.ts, p.h * stf, und);
-    if (p.s_second >= 0 || (p.full && p.s_first >= 0)) p.psi[idx] = psi2;
+    if (p.s_first >= 0) {
+      const R dT = th_t1 - p.t_ref;
+      const R dkc = thermal_dk(dT, p.dk);
+      const HalfStepT<R> c1t = thermal_coefs(ph1, p.kf, p.ks, rho,
+                                             expi_neg_small(dkc * (qdz * stf)), dT, p.lens_f,
+                                             p.lens_sh);
+      rk4_cell_t(a, b, c1t, p.tf, p.ts, p.h * stf, und);
+      if (p.full) psi += dkc * p.dz;
+    }
+    // Psi at the start of the newest step touched
+    if (p.s_second >= 0 || (p.full && p.s_first >= 0)) p.psi[idx] = psi;
   } else {
+    const HalfStep<R> c2 = coefs_of(ph2, p.kf, p.ks);
+    const HalfStep<R> c1 = coefs_of(ph1, p.kf, p.ks);
     if (p.s_second >= 0) rk4_cell(a, b, c2, p.tf, p.ts, p.h, und);
     if (p.heat) gp(p.heat)[idx] = heat_density(a, b, p);
     if (p.s_first >= 0) rk4_cell(a, b, c1, p.tf, p.ts, p.h * stf, und);
