@@ -151,6 +151,9 @@ def main(argv=None):
                     help="comma-separated extra lines to run (default: all of "
                          "batched, fwd_adj, c5_forward, c1_complex128, thermal_fwd_adj, lnl, thermal, "
                          "self_consistent)")
+    ap.add_argument("--progress", action="store_true",
+                    help="print a line to stderr after each step of the extra lines "
+                         "(for runs under a profiler)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 64 MiB device copy from a cache-cold source "
                          "(reference for the HBM byte counters)")
@@ -259,6 +262,7 @@ def main(argv=None):
     if not args.no_extras:
         try:
             from paper_2410_04994_amd import extras
+            extras.PROGRESS = args.progress
             only = [x for x in args.extras.split(",") if x] or None
             out["extras"] = extras.run_all(dev, only)
         except Exception as exc:  # extras must never hide the main line

@@ -6,14 +6,27 @@ equation for the heat of the 256 x 256 x 1000 march, and the self-consistent
 field <-> temperature loop of the 50 W workload (512 x 512 x 2000)."""
 from __future__ import annotations
 
+import sys
 import time
+
+# When set, each finished repetition and line prints a line to stderr (for runs
+# under a profiler, where a line can take minutes).
+PROGRESS = False
+
+
+def _progress(msg: str) -> None:
+    if PROGRESS:
+        print(f"extras: {msg}", file=sys.stderr, flush=True)
 
 
 def _timed(fn, reps, torch):
     torch.cuda.synchronize()
     t = time.perf_counter()
-    for _ in range(reps):
+    for i in range(reps):
         fn()
+        if PROGRESS:
+            torch.cuda.synchronize()
+            _progress(f"repetition {i + 1}/{reps}")
     torch.cuda.synchronize()
     return (time.perf_counter() - t) / reps
 
@@ -47,6 +60,7 @@ def batched(device, reps=3, split="NLN"):
 
     run()                      # direct run + graph capture
     run()
+    _progress("batch warm-up done")
     sec = _timed(run, reps, torch)
     cells = sum(w.cell_steps for w in wls)
     scheds = sorted({p.describe().split("batch(")[1].split(")")[0] for p in plans})
@@ -391,4 +405,5 @@ def run_all(device, only=None) -> dict:
             out[name] = fn(device)
         except Exception as exc:
             out[name] = {"error": f"{type(exc).__name__}: {exc}"}
+        _progress(f"{name} done")
     return out
