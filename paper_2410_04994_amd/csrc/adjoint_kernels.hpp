@@ -303,8 +303,6 @@ struct RowAdjTArgs {
   DkT<R> dk;              // mismatch shift of each cell's temperature
 };
 
-// Pull-back of one cell through the first half-step of s_first and the second
-// half-step of s_second (either may be absent), from the staged forward state.
 // Per-cell inputs of the adjoint row pass that do not depend on the
 // cotangent: the staged forward state, the stage coefficients and, with a
 // temperature field, Psi, the carry and the two samples.  Loading them before
@@ -346,6 +344,8 @@ __device__ __forceinline__ AdjPre<R, TH> adj_load(const RowAdjArgs<R>& p, const 
   return a;
 }
 
+// Pull-back of one cell through the first half-step of s_first and the second
+// half-step of s_second (either may be absent), from the staged forward state.
 template <typename R, bool TH>
 __device__ __forceinline__ void adj_cell(const RowAdjArgs<R>& p, const RowAdjTArgs<R>& q,
                                          const AdjPre<R, TH>& pre, size_t idx, cx<R>& la,
