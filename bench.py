@@ -67,22 +67,51 @@ def measured_traffic(kernel: str, launch_bytes: float):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
-# One oracle process of the CPU baseline: marches the first `steps` z-steps of
-# the benchmark workload and prints the seconds it took (the import and input
-# set-up are not timed).
+# One oracle process of the CPU baseline.  argv: kind, steps, rank, processes.
+# It times the oracle on its share of a bounded sample of one config and prints
+# "<seconds> <cell-steps>" (imports and input set-up are not timed):
+#   c2  the benchmark workload, first `steps` z-steps
+#   c1  the 64 x 64 x 200 complex128 workload, whole crystal
+#   c5  the 512 x 512 x 2000 temperature-field workload, first `steps` z-steps
+#   c4  forward + adjoint (loss P_SH, per-step mismatch gradient) of the
+#       differentiation workload's grid over a crystal of `steps` z-steps
+#   c3  every `processes`-th instance of the first 64 of the batch sweep,
+#       starting at `rank`, first `steps` z-steps each
 _ORACLE_SAMPLE = """
 import sys, time
 sys.path.insert(0, {root!r})
 import numpy as np
 import workloads
-from oracle import beams, ssfm
-wl = workloads.c2_plain_c64()
-p = wl.params()
-a0 = beams.input_pump(p, wl.power, wl.w0, wl.focus, workloads.phase_noise(wl)).astype(np.complex64)
-b0 = np.zeros_like(a0)
-t = time.perf_counter()
-ssfm.propagate(p, a0, b0, s_end={steps})
-print(time.perf_counter() - t)
+from oracle import beams, ssfm, adjoint
+kind, steps, rank, procs = sys.argv[1], int(sys.argv[2]), int(sys.argv[3]), int(sys.argv[4])
+def inputs(wl):
+    p = wl.params()
+    th = workloads.phase_noise(wl) if wl.phase_noise_std else None
+    a0 = beams.input_pump(p, wl.power, wl.w0, wl.focus, th)
+    return p, a0, np.zeros_like(a0)
+if kind == "c3":
+    cases = [inputs(w) + (w.nx * w.ny * steps,) for w in workloads.c3_batch()[:64][rank::procs]]
+    t = time.perf_counter()
+    for p, a0, b0, _ in cases:
+        ssfm.propagate(p, a0, b0, s_end=steps)
+    print(time.perf_counter() - t, sum(c[3] for c in cases))
+else:
+    wl = {{"c1": workloads.c1_plain_fp64, "c2": workloads.c2_plain_c64,
+           "c4": workloads.c4_diff_c64, "c5": workloads.c5_thermal_c64}}[kind]()
+    if kind == "c4":
+        wl = wl.with_(nz=steps)
+    p, a0, b0 = inputs(wl)
+    if kind == "c2":
+        a0 = a0.astype(np.complex64)
+    temp = workloads.RadialTemperature(wl) if kind == "c5" else None
+    n = wl.nz if kind in ("c1", "c4") else steps
+    t = time.perf_counter()
+    if kind == "c4":
+        adjoint.adjoint(p, a0, b0, np.zeros_like(a0), np.zeros_like(a0),
+                        dk_z=np.full(n, wl.dk0), power_weights=(0.0, 1.0))
+    else:
+        ssfm.propagate(p, a0, b0, temp=temp, s_end=n)
+    print(time.perf_counter() - t, wl.nx * wl.ny * n)
 """
 
 
@@ -105,38 +134,65 @@ def host_cores() -> int:
     return max(1, min(16, n))
 
 
-def cpu_baseline(wl, sample_steps: int):
+def _oracle_runs(kind: str, steps: int, n: int):
+    """n child processes of the oracle sample at once (ranks 0..n-1); returns
+    [(seconds, cell_steps)] per process.  The children touch no GPU."""
+    import subprocess
+    code = _ORACLE_SAMPLE.format(root=ROOT)
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    procs = [subprocess.Popen([sys.executable, "-c", code, kind, str(steps), str(r), str(n)],
+                              stdout=subprocess.PIPE, env=env, text=True) for r in range(n)]
+    res = []
+    for pr in procs:
+        out, _ = pr.communicate()
+        if pr.returncode != 0:
+            raise RuntimeError(f"oracle sample process failed ({pr.returncode})")
+        sec, cells = out.strip().splitlines()[-1].split()
+        res.append((float(sec), int(cells)))
+    return res
+
+
+def _rate(runs):
+    return round(sum(c for _, c in runs) / max(s for s, _ in runs), 1)
+
+
+def cpu_baseline(wl, sample_steps: int, other_configs: bool = True):
     """Time the FP64 oracle (as it stands) on the first `sample_steps` z-steps
     of the workload: one process on one core, then one independent copy per
     host core at once (the oracle's FFTs and pointwise steps are single
-    threaded, so independent marches are how it uses more cores).  Each copy
-    is a child Python process that touches no GPU."""
-    import subprocess
-    code = _ORACLE_SAMPLE.format(root=ROOT, steps=sample_steps)
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-
-    def run(n):
-        procs = [subprocess.Popen([sys.executable, "-c", code], stdout=subprocess.PIPE, env=env,
-                                  text=True) for _ in range(n)]
-        secs = []
-        for pr in procs:
-            out, _ = pr.communicate()
-            if pr.returncode != 0:
-                raise RuntimeError(f"oracle sample process failed ({pr.returncode})")
-            secs.append(float(out.strip().splitlines()[-1]))
-        return secs
-
-    cells = wl.nx * wl.ny * sample_steps
-    one = run(1)[0]
+    threaded, so independent marches are how it uses more cores).  With
+    `other_configs`, bounded samples of the other configs as well: the batch
+    sweep as a pool of processes over its instances, and the others on one
+    core (and, for the temperature-field march, on every core)."""
     cores = host_cores()
-    many = run(cores)
-    return {"value": round(cells * cores / max(many), 1), "unit": "cell-steps/s", "cores": cores,
-            "kind": "oracle",
-            "sample": (f"{wl.name}: first {sample_steps} of {wl.nz} z-steps per process, numpy "
-                       f"FP64; {cores} independent processes at once (value: total cell-steps / "
-                       f"slowest process)"),
-            "single_core": {"value": round(cells / one, 1), "cores": 1, "seconds": round(one, 3)},
-            "cpu_model": cpu_model(), "host_cpus_visible": os.cpu_count()}
+    one = _oracle_runs("c2", sample_steps, 1)
+    many = _oracle_runs("c2", sample_steps, cores)
+    out = {"value": _rate(many), "unit": "cell-steps/s", "cores": cores, "kind": "oracle",
+           "sample": (f"{wl.name}: first {sample_steps} of {wl.nz} z-steps per process, numpy "
+                      f"FP64; {cores} independent processes at once (value: total cell-steps / "
+                      f"slowest process)"),
+           "single_core": {"value": _rate(one), "cores": 1, "seconds": round(one[0][0], 3)},
+           "cpu_model": cpu_model(), "host_cpus_visible": os.cpu_count()}
+    if other_configs:
+        oc = {}
+        r = _oracle_runs("c1", 0, 1)
+        oc["c1_plain_fp64_64x64x200"] = {"value": _rate(r), "cores": 1, "sample": "whole crystal"}
+        r = _oracle_runs("c3", 40, cores)
+        oc["c3_batch"] = {"value": _rate(r), "cores": cores,
+                          "sample": (f"first 64 of the 512 instances, first 40 z-steps each, over "
+                                     f"{cores} processes (total cell-steps / slowest process)")}
+        r = _oracle_runs("c4", 20, 1)
+        oc["c4_diff_c64_fwd_adj"] = {"value": _rate(r), "cores": 1,
+                                     "sample": ("forward + adjoint on the 256 x 256 grid over a "
+                                                "20-step crystal")}
+        r1 = _oracle_runs("c5", 10, 1)
+        rn = _oracle_runs("c5", 10, cores)
+        oc["c5_thermal_c64_512x512x2000"] = {
+            "value": _rate(rn), "cores": cores, "single_core": _rate(r1),
+            "sample": (f"first 10 of 2000 z-steps with the temperature field, one process and "
+                       f"{cores} processes at once")}
+        out["other_configs"] = oc
+    return out
 
 
 def main(argv=None):
@@ -146,6 +202,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sample-steps", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-main-only", action="store_true",
+                    help="time the oracle on the benchmark workload only")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="",
                     help="comma-separated extra lines to run (default: all of "
@@ -268,7 +326,8 @@ def main(argv=None):
         except Exception as exc:  # extras must never hide the main line
             out["extras"] = {"error": f"{type(exc).__name__}: {exc}"}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps,
+                                           not args.cpu_baseline_main_only)
     print(json.dumps(out))
     return 0
 
