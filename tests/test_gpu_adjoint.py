@@ -212,6 +212,39 @@ def test_thermal_adjoint_matches_oracle(dtype, tol, cubic):
     assert rel(got["g_t_moments"], ref["g_t_moments"]) < tol
 
 
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-4)])
+def test_thermal_adjoint_on_narrow_row_schedules(dtype, tol):
+    """The temperature-field adjoint row pass with several cells per thread
+    (schedules the defaults do not pick), with the cubic and grating dk(T),
+    against the oracle's reverse-mode gradient."""
+    from paper_2410_04994_amd import Plan
+    wl, temp = thermal_small()
+    wl = wl.with_(**CUBIC_DK)
+    rdt = np.float32 if dtype == "c64" else np.float64
+    temp = temp.astype(rdt)
+    a0, b0 = inputs(wl, dtype)
+    w = (0.2, 1.0)
+    ref = oadj.adjoint(wl.params(), a0.astype(complex), b0.astype(complex), np.zeros(a0.shape, complex),
+                       np.zeros(a0.shape, complex), temp=temp.astype(np.float64), power_weights=w)
+    plan = Plan(wl.params(), dtype, checkpoint_every=5)
+    tried = 0
+    for re_, rw in ((4, 64), (8, 64), (4, 256)):
+        try:
+            plan.set_schedule(re_, rw, 0, 0)
+        except Exception:
+            continue
+        res = plan.adjoint(cuda(a0), cuda(b0), power_weights=cuda(np.asarray(w)), temp=cuda(temp),
+                           want_dk=True, want_t=True)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in res.items()}
+        msg = plan.describe()
+        assert rel(got["g_f"], ref["g_f"]) < tol, msg
+        assert rel(got["g_dk"], ref["g_dk"]) < tol, msg
+        assert rel(got["g_t_moments"], ref["g_t_moments"]) < tol, msg
+        tried += 1
+    assert tried >= 1
+
+
 def test_thermal_scalar_gradients_by_finite_differences():
     """dP_SH/d(dT scale) and dP_SH/dT0 of the thermal-lens workload shape,
     through torch, against central differences of the complex128 march."""

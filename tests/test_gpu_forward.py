@@ -251,6 +251,28 @@ def test_temperature_field_cubic_mismatch(dtype, grating):
         assert rel(ref["a_sh"], nog["a_sh"]) > 1e-3
 
 
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_temperature_field_on_every_row_schedule(dtype):
+    """The temperature-field row pass in every built row schedule, the narrow
+    ones (several cells per thread) included, which the default schedules do
+    not pick: dk(T) with the cubic and the grating term, against the oracle."""
+    wl, temp = thermal_case(n=64, nz=24)
+    wl = wl.with_(ddk_dT=60.0, ddk_dT2=-15.0, ddk_dT3=4.0, grating_period=workloads.GRATING_PERIOD,
+                  grating_a=workloads.GRATING_A, grating_b=workloads.GRATING_B)
+    plan = make_plan(wl, dtype)
+    a0, b0 = inputs(wl, dtype)
+    ref = run_oracle(wl, a0, b0, temp=temp.astype(np.float64))
+    tried = []
+    for re_, rw in ((1, 256), (4, 64), (4, 256), (8, 64), (8, 256), (16, 64)):
+        try:
+            plan.set_schedule(re_, rw, 0, 0)
+        except Exception:
+            continue
+        compare(wl, run_gpu(plan, a0, b0, temp=temp), ref, dtype, "T field " + plan.describe())
+        tried.append(re_)
+    assert 1 in tried and any(e > 1 for e in tried)
+
+
 def test_temperature_field_resume_and_profile():
     wl, temp = thermal_case(n=32, nz=24)
     rng = np.random.Generator(np.random.PCG64(3))
