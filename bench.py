@@ -208,7 +208,7 @@ def main(argv=None):
     ap.add_argument("--extras", default="",
                     help="comma-separated extra lines to run (default: all of "
                          "batched, fwd_adj, c5_forward, c1_complex128, thermal_fwd_adj, lnl, thermal, "
-                         "self_consistent)")
+                         "self_consistent, latency_floor)")
     ap.add_argument("--progress", action="store_true",
                     help="print a line to stderr after each step of the extra lines "
                          "(for runs under a profiler)")
@@ -323,6 +323,11 @@ def main(argv=None):
             extras.PROGRESS = args.progress
             only = [x for x in args.extras.split(",") if x] or None
             out["extras"] = extras.run_all(dev, only)
+            lf = out["extras"].get("latency_floor")
+            if isinstance(lf, dict) and "two_pass_step_floor_us" in lf:
+                step_us = ms_per_step * 1e3 / wl.nz
+                lf["march_step_us"] = round(step_us, 3)
+                lf["march_fraction_of_floor"] = round(lf["two_pass_step_floor_us"] / step_us, 4)
         except Exception as exc:  # extras must never hide the main line
             out["extras"] = {"error": f"{type(exc).__name__}: {exc}"}
     if not args.no_cpu_baseline:

@@ -388,11 +388,55 @@ def lnl(device, steps=5):
     return out
 
 
+def latency_floor(device, launches=2000, reps=3):
+    """A measured floor for the 256 x 256 single-instance march: any design
+    with two device-wide exchanges per z-step launches (at least) two kernels
+    per step, each of which reads and writes the whole state (both complex64
+    fields, 1 MiB) once.  Timed with plain library kernels replayed from a
+    HIP graph, like the march: a launch that touches one element (the launch
+    gap alone) and a launch that adds a constant to the whole state in place
+    (the gap plus one read and one write of the state from the Infinity Cache,
+    where the march's state lives between passes)."""
+    import torch
+    state = torch.zeros(2 * 256 * 256 * 2, dtype=torch.float32, device=device)
+    tiny = torch.zeros(1, dtype=torch.float32, device=device)
+
+    def per_launch_us(t):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(3):
+                t.add_(1.0)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(launches):
+                t.add_(1.0)
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.replay()
+        torch.cuda.synchronize()
+        us = (time.perf_counter() - t0) / (reps * launches) * 1e6
+        del g
+        return us
+
+    gap = per_launch_us(tiny)
+    rw = per_launch_us(state)
+    return {"graph_launch_one_element_us": round(gap, 3), "graph_launch_state_rw_us": round(rw, 3),
+            "two_pass_step_floor_us": round(2 * rw, 3),
+            "note": ("floor of a z-step with two device-wide exchanges at 256 x 256: two "
+                     "graph-replayed launches that each read and write the 1 MiB state once")}
+
+
 def run_all(device, only=None) -> dict:
     """Every extra line, or those named in `only`."""
     lines = (("batched", batched), ("fwd_adj", fwd_adj), ("c5_forward", c5_forward),
              ("c1_complex128", c1_complex128), ("thermal_fwd_adj", thermal_fwd_adj),
-             ("lnl", lnl), ("thermal", thermal), ("self_consistent", self_consistent_loop))
+             ("lnl", lnl), ("thermal", thermal), ("self_consistent", self_consistent_loop),
+             ("latency_floor", latency_floor))
     known = [name for name, _ in lines]
     unknown = [x for x in (only or []) if x not in known]
     if unknown:
