@@ -46,31 +46,31 @@ __device__ __forceinline__ void nl_vjp(cx<R> a, cx<R> b, cx<R> cf, cx<R> cs, R t
 // (la, lb)  in: cotangent of the output; out: cotangent of the input
 // gphi, gphit accumulate dL/dphi and dL/dphi * t over the four stages, where
 // the stage points are t0, t0 + h/2, t0 + h/2, t0 + h.
-template <typename R>
-__device__ __forceinline__ void rk4_vjp(cx<R> a, cx<R> b, cx<R>& la, cx<R>& lb,
-                                        const HalfStep<R>& c, R tf, R ts, R h, bool und, R t0,
+template <bool UND, typename R>
+__device__ __forceinline__ void rk4_vjp_u(cx<R> a, cx<R> b, cx<R>& la, cx<R>& lb,
+                                        const HalfStep<R>& c, R tf, R ts, R h, R t0,
                                         R& gphi, R& gphit) {
   const R h2 = h * (R)0.5;
   cx<R> k1a, k1b, k2a, k2b, k3a, k3b;
-  nl_rhs(a, b, c.cf[0], c.cs[0], tf, ts, und, k1a, k1b);
+  nl_rhs(a, b, c.cf[0], c.cs[0], tf, ts, UND, k1a, k1b);
   const cx<R> u2a = a + scale(k1a, h2), u2b = b + scale(k1b, h2);
-  nl_rhs(u2a, u2b, c.cf[1], c.cs[1], tf, ts, und, k2a, k2b);
+  nl_rhs(u2a, u2b, c.cf[1], c.cs[1], tf, ts, UND, k2a, k2b);
   const cx<R> u3a = a + scale(k2a, h2), u3b = b + scale(k2b, h2);
-  nl_rhs(u3a, u3b, c.cf[1], c.cs[1], tf, ts, und, k3a, k3b);
+  nl_rhs(u3a, u3b, c.cf[1], c.cs[1], tf, ts, UND, k3a, k3b);
   const cx<R> u4a = a + scale(k3a, h), u4b = b + scale(k3b, h);
   const R h6 = h / (R)6, h3 = h / (R)3;
   cx<R> ga, gb;
   R dp;
   // stage 4
   cx<R> kba = scale(la, h6), kbb = scale(lb, h6);
-  nl_vjp(u4a, u4b, c.cf[2], c.cs[2], tf, ts, und, kba, kbb, ga, gb, dp);
+  nl_vjp(u4a, u4b, c.cf[2], c.cs[2], tf, ts, UND, kba, kbb, ga, gb, dp);
   cx<R> sa = ga, sb = gb;
   gphi += dp;
   gphit += dp * (t0 + h);
   // stage 3
   kba = scale(la, h3) + scale(ga, h);
   kbb = scale(lb, h3) + scale(gb, h);
-  nl_vjp(u3a, u3b, c.cf[1], c.cs[1], tf, ts, und, kba, kbb, ga, gb, dp);
+  nl_vjp(u3a, u3b, c.cf[1], c.cs[1], tf, ts, UND, kba, kbb, ga, gb, dp);
   sa = sa + ga;
   sb = sb + gb;
   gphi += dp;
@@ -78,7 +78,7 @@ __device__ __forceinline__ void rk4_vjp(cx<R> a, cx<R> b, cx<R>& la, cx<R>& lb,
   // stage 2
   kba = scale(la, h3) + scale(ga, h2);
   kbb = scale(lb, h3) + scale(gb, h2);
-  nl_vjp(u2a, u2b, c.cf[1], c.cs[1], tf, ts, und, kba, kbb, ga, gb, dp);
+  nl_vjp(u2a, u2b, c.cf[1], c.cs[1], tf, ts, UND, kba, kbb, ga, gb, dp);
   sa = sa + ga;
   sb = sb + gb;
   gphi += dp;
@@ -86,13 +86,20 @@ __device__ __forceinline__ void rk4_vjp(cx<R> a, cx<R> b, cx<R>& la, cx<R>& lb,
   // stage 1
   kba = scale(la, h6) + scale(ga, h2);
   kbb = scale(lb, h6) + scale(gb, h2);
-  nl_vjp(a, b, c.cf[0], c.cs[0], tf, ts, und, kba, kbb, ga, gb, dp);
+  nl_vjp(a, b, c.cf[0], c.cs[0], tf, ts, UND, kba, kbb, ga, gb, dp);
   sa = sa + ga;
   sb = sb + gb;
   gphi += dp;
   gphit += dp * t0;
   la = la + sa;
   lb = lb + sb;
+}
+template <typename R>
+__device__ __forceinline__ void rk4_vjp(cx<R> a, cx<R> b, cx<R>& la, cx<R>& lb,
+                                        const HalfStep<R>& c, R tf, R ts, R h, bool und, R t0,
+                                        R& gphi, R& gphit) {
+  if (und) rk4_vjp_u<true>(a, b, la, lb, c, tf, ts, h, t0, gphi, gphit);
+  else rk4_vjp_u<false>(a, b, la, lb, c, tf, ts, h, t0, gphi, gphit);
 }
 
 template <typename R>
@@ -235,30 +242,30 @@ __device__ __forceinline__ void nl_vjp_t(cx<R> a, cx<R> b, cx<R> cf, cx<R> cs, R
   }
 }
 
-template <typename R>
-__device__ __forceinline__ void rk4_vjp_t(cx<R> a, cx<R> b, cx<R>& la, cx<R>& lb,
+template <bool UND, typename R>
+__device__ __forceinline__ void rk4_vjp_t_u(cx<R> a, cx<R> b, cx<R>& la, cx<R>& lb,
                                           const HalfStepT<R>& c, R tf, R ts, R lf, R ls, R h,
-                                          bool und, R t0, R& gphi, R& gphit, R& glens) {
+                                            R t0, R& gphi, R& gphit, R& glens) {
   const R h2 = h * (R)0.5;
   cx<R> k1a, k1b, k2a, k2b, k3a, k3b;
-  nl_rhs_t(a, b, c.cf[0], c.cs[0], tf, ts, c.gf, c.gs, und, k1a, k1b);
+  nl_rhs_t(a, b, c.cf[0], c.cs[0], tf, ts, c.gf, c.gs, UND, k1a, k1b);
   const cx<R> u2a = a + scale(k1a, h2), u2b = b + scale(k1b, h2);
-  nl_rhs_t(u2a, u2b, c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, und, k2a, k2b);
+  nl_rhs_t(u2a, u2b, c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, UND, k2a, k2b);
   const cx<R> u3a = a + scale(k2a, h2), u3b = b + scale(k2b, h2);
-  nl_rhs_t(u3a, u3b, c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, und, k3a, k3b);
+  nl_rhs_t(u3a, u3b, c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, UND, k3a, k3b);
   const cx<R> u4a = a + scale(k3a, h), u4b = b + scale(k3b, h);
   const R h6 = h / (R)6, h3 = h / (R)3;
   cx<R> ga, gb;
   R dp, dl;
   cx<R> kba = scale(la, h6), kbb = scale(lb, h6);
-  nl_vjp_t(u4a, u4b, c.cf[2], c.cs[2], tf, ts, c.gf, c.gs, lf, ls, und, kba, kbb, ga, gb, dp, dl);
+  nl_vjp_t(u4a, u4b, c.cf[2], c.cs[2], tf, ts, c.gf, c.gs, lf, ls, UND, kba, kbb, ga, gb, dp, dl);
   cx<R> sa = ga, sb = gb;
   gphi += dp;
   gphit += dp * (t0 + h);
   glens += dl;
   kba = scale(la, h3) + scale(ga, h);
   kbb = scale(lb, h3) + scale(gb, h);
-  nl_vjp_t(u3a, u3b, c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, lf, ls, und, kba, kbb, ga, gb, dp, dl);
+  nl_vjp_t(u3a, u3b, c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, lf, ls, UND, kba, kbb, ga, gb, dp, dl);
   sa = sa + ga;
   sb = sb + gb;
   gphi += dp;
@@ -266,7 +273,7 @@ __device__ __forceinline__ void rk4_vjp_t(cx<R> a, cx<R> b, cx<R>& la, cx<R>& lb
   glens += dl;
   kba = scale(la, h3) + scale(ga, h2);
   kbb = scale(lb, h3) + scale(gb, h2);
-  nl_vjp_t(u2a, u2b, c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, lf, ls, und, kba, kbb, ga, gb, dp, dl);
+  nl_vjp_t(u2a, u2b, c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, lf, ls, UND, kba, kbb, ga, gb, dp, dl);
   sa = sa + ga;
   sb = sb + gb;
   gphi += dp;
@@ -274,7 +281,7 @@ __device__ __forceinline__ void rk4_vjp_t(cx<R> a, cx<R> b, cx<R>& la, cx<R>& lb
   glens += dl;
   kba = scale(la, h6) + scale(ga, h2);
   kbb = scale(lb, h6) + scale(gb, h2);
-  nl_vjp_t(a, b, c.cf[0], c.cs[0], tf, ts, c.gf, c.gs, lf, ls, und, kba, kbb, ga, gb, dp, dl);
+  nl_vjp_t(a, b, c.cf[0], c.cs[0], tf, ts, c.gf, c.gs, lf, ls, UND, kba, kbb, ga, gb, dp, dl);
   sa = sa + ga;
   sb = sb + gb;
   gphi += dp;
@@ -282,6 +289,13 @@ __device__ __forceinline__ void rk4_vjp_t(cx<R> a, cx<R> b, cx<R>& la, cx<R>& lb
   glens += dl;
   la = la + sa;
   lb = lb + sb;
+}
+template <typename R>
+__device__ __forceinline__ void rk4_vjp_t(cx<R> a, cx<R> b, cx<R>& la, cx<R>& lb,
+                                          const HalfStepT<R>& c, R tf, R ts, R lf, R ls, R h,
+                                          bool und, R t0, R& gphi, R& gphit, R& glens) {
+  if (und) rk4_vjp_t_u<true>(a, b, la, lb, c, tf, ts, lf, ls, h, t0, gphi, gphit, glens);
+  else rk4_vjp_t_u<false>(a, b, la, lb, c, tf, ts, lf, ls, h, t0, gphi, gphit, glens);
 }
 
 // Per-cell carry of the thermal reverse sweep:

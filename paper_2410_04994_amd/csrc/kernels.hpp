@@ -84,18 +84,38 @@ __device__ __forceinline__ HalfStep<R> half_step_coefs(P __restrict__ e, R kf, R
 
 // Classical RK4 over one half-step of length h with stage points t0, t0 + h/2,
 // t0 + h/2, t0 + h (Sec. 3; the RK4 of the paper's nonlinear step).
-template <typename R>
-__device__ __forceinline__ void rk4_cell(cx<R>& a, cx<R>& b, const HalfStep<R>& c, R tf, R ts,
-                                         R h, bool und) {
+template <bool UND, typename R>
+__device__ __forceinline__ void rk4_cell_u(cx<R>& a, cx<R>& b, const HalfStep<R>& c, R tf, R ts,
+                                           R h) {
   const R h2 = h * (R)0.5;
   cx<R> k1a, k1b, k2a, k2b, k3a, k3b, k4a, k4b;
-  nl_rhs(a, b, c.cf[0], c.cs[0], tf, ts, und, k1a, k1b);
-  nl_rhs(a + scale(k1a, h2), b + scale(k1b, h2), c.cf[1], c.cs[1], tf, ts, und, k2a, k2b);
-  nl_rhs(a + scale(k2a, h2), b + scale(k2b, h2), c.cf[1], c.cs[1], tf, ts, und, k3a, k3b);
-  nl_rhs(a + scale(k3a, h), b + scale(k3b, h), c.cf[2], c.cs[2], tf, ts, und, k4a, k4b);
+  nl_rhs(a, b, c.cf[0], c.cs[0], tf, ts, UND, k1a, k1b);
+  nl_rhs(a + scale(k1a, h2), b + scale(k1b, h2), c.cf[1], c.cs[1], tf, ts, UND, k2a, k2b);
+  nl_rhs(a + scale(k2a, h2), b + scale(k2b, h2), c.cf[1], c.cs[1], tf, ts, UND, k3a, k3b);
+  nl_rhs(a + scale(k3a, h), b + scale(k3b, h), c.cf[2], c.cs[2], tf, ts, UND, k4a, k4b);
   const R h6 = h / (R)6;
   a = a + scale(k1a + scale(k2a + k3a, (R)2) + k4a, h6);
   b = b + scale(k1b + scale(k2b + k3b, (R)2) + k4b, h6);
+}
+// The undepleted flag is uniform over a launch: one branch per half-step
+// chooses a body specialised for it, instead of a branch in every stage.
+template <typename R>
+__device__ __forceinline__ void rk4_cell(cx<R>& a, cx<R>& b, const HalfStep<R>& c, R tf, R ts,
+                                         R h, bool und) {
+  if (und) rk4_cell_u<true>(a, b, c, tf, ts, h);
+  else rk4_cell_u<false>(a, b, c, tf, ts, h);
+}
+// The same for the E cells of a thread.
+template <int E, typename R>
+__device__ __forceinline__ void rk4_cells(cx<R> (&a)[E], cx<R> (&b)[E], const HalfStep<R>& c, R tf,
+                                          R ts, R h, bool und) {
+  if (und) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) rk4_cell_u<true>(a[m], b[m], c, tf, ts, h);
+  } else {
+#pragma unroll
+    for (int m = 0; m < E; ++m) rk4_cell_u<false>(a[m], b[m], c, tf, ts, h);
+  }
 }
 
 // ---------------------------------------------------------------- temperature
@@ -232,21 +252,27 @@ __device__ __forceinline__ void nl_rhs_t(cx<R> a, cx<R> b, cx<R> cf, cx<R> cs, R
   if (!und) fa = fa + cx<R>{gf * a.im, -gf * a.re};
 }
 
-template <typename R>
-__device__ __forceinline__ void rk4_cell_t(cx<R>& a, cx<R>& b, const HalfStepT<R>& c, R tf, R ts,
-                                           R h, bool und) {
+template <bool UND, typename R>
+__device__ __forceinline__ void rk4_cell_t_u(cx<R>& a, cx<R>& b, const HalfStepT<R>& c, R tf, R ts,
+                                             R h) {
   const R h2 = h * (R)0.5;
   cx<R> k1a, k1b, k2a, k2b, k3a, k3b, k4a, k4b;
-  nl_rhs_t(a, b, c.cf[0], c.cs[0], tf, ts, c.gf, c.gs, und, k1a, k1b);
-  nl_rhs_t(a + scale(k1a, h2), b + scale(k1b, h2), c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, und, k2a,
+  nl_rhs_t(a, b, c.cf[0], c.cs[0], tf, ts, c.gf, c.gs, UND, k1a, k1b);
+  nl_rhs_t(a + scale(k1a, h2), b + scale(k1b, h2), c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, UND, k2a,
            k2b);
-  nl_rhs_t(a + scale(k2a, h2), b + scale(k2b, h2), c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, und, k3a,
+  nl_rhs_t(a + scale(k2a, h2), b + scale(k2b, h2), c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, UND, k3a,
            k3b);
-  nl_rhs_t(a + scale(k3a, h), b + scale(k3b, h), c.cf[2], c.cs[2], tf, ts, c.gf, c.gs, und, k4a,
+  nl_rhs_t(a + scale(k3a, h), b + scale(k3b, h), c.cf[2], c.cs[2], tf, ts, c.gf, c.gs, UND, k4a,
            k4b);
   const R h6 = h / (R)6;
   a = a + scale(k1a + scale(k2a + k3a, (R)2) + k4a, h6);
   b = b + scale(k1b + scale(k2b + k3b, (R)2) + k4b, h6);
+}
+template <typename R>
+__device__ __forceinline__ void rk4_cell_t(cx<R>& a, cx<R>& b, const HalfStepT<R>& c, R tf, R ts,
+                                           R h, bool und) {
+  if (und) rk4_cell_t_u<true>(a, b, c, tf, ts, h);
+  else rk4_cell_t_u<false>(a, b, c, tf, ts, h);
 }
 
 // ---------------------------------------------------------------- row pass
@@ -404,19 +430,13 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
       if (p.s_second >= 0 || (p.full && p.s_first >= 0)) p.psi[idx] = psi;
     }
   } else {
-    if (p.s_second >= 0) {
-#pragma unroll
-      for (int m = 0; m < E; ++m) rk4_cell(va[m], vb[m], c2, p.tf, p.ts, p.h, und);
-    }
+    if (p.s_second >= 0) rk4_cells(va, vb, c2, p.tf, p.ts, p.h, und);
     if (p.heat) {
       const auto ht = gp(p.heat);
 #pragma unroll
       for (int m = 0; m < E; ++m) ht[row + t + G * m] = heat_density(va[m], vb[m], p);
     }
-    if (p.s_first >= 0) {
-#pragma unroll
-      for (int m = 0; m < E; ++m) rk4_cell(va[m], vb[m], c1, p.tf, p.ts, p.h * stf, und);
-    }
+    if (p.s_first >= 0) rk4_cells(va, vb, c1, p.tf, p.ts, p.h * stf, und);
   }
   if (p.fwd_out) {
     fft_pre<R, N, G, false, 1, (G <= 64)>(va, a0, a1, t, twr);
