@@ -63,6 +63,17 @@ def test_config2_full_size():
     assert es < 5e-5 and eps < 5e-6
 
 
+def test_config2_full_size_in_the_lnl_order():
+    """The benchmark workload (256 x 256 x 1000) in the L/2 - N - L/2 order,
+    whole crystal, against the oracle's march in the same order."""
+    from paper_2410_04994_amd import autotune
+    wl = workloads.c2_plain_c64().with_(split="LNL")
+    plan = make_plan(wl)
+    autotune.tune_single(plan)
+    a0, b0 = inputs(wl)
+    compare(wl, run_gpu(plan, a0, b0), run_oracle(wl, a0, b0), "c64", "LNL " + plan.describe())
+
+
 def test_autotuner_picks_a_correct_schedule(tmp_path, monkeypatch):
     from paper_2410_04994_amd import autotune
     monkeypatch.setenv("SHG_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
