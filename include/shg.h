@@ -158,7 +158,7 @@ int shg_propagate(shg_plan *plan, void *a_f, void *a_sh, const double *dk_z,
 /* shg_propagate for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, hosts that forbid hipMalloc).  Same
  * arguments and results as shg_propagate without `workspace`: the march's
- * workspace (phase table, power partials, temperature phase) is a static
+ * workspace (stage-coefficient table, power partials, temperature phase) is a static
  * device array of 4 MiB per GPU, held until the process ends.  The call
  * allocates nothing and creates no graph: the passes are enqueued one by one
  * on `stream` (so it can be recorded into a caller's graph).  Every call on a
@@ -167,7 +167,7 @@ int shg_propagate(shg_plan *plan, void *a_f, void *a_sh, const double *dk_z,
  * the array needs to survive between calls.  The current device must be the
  * plan's.  Timing mode (shg_plan_set_timing) does not apply.
  * Errors: as shg_propagate; SHG_EINVAL also when shg_workspace_bytes(plan, 0)
- * exceeds 4 MiB (nz above about 26000 for 512x512 complex128, about 78000
+ * exceeds 4 MiB (nz above about 13000 for 512x512 complex128, about 39000
  * for 512x512 complex64), when the current device is not the plan's,
  * or for a plan with SHG_CHECK_FINITE; SHG_EDEVICE when the array's device
  * address could not be obtained. */

@@ -283,7 +283,7 @@ static int adjoint_t(Plan& pl, const void* a_f_in, const void* a_sh_in, const do
   ra.la = la;
   ra.lb = lb;
   ra.tw = (const Tw<R>*)pl.tw_x;
-  ra.phase = (const cx<R>*)fws;
+  ra.phase = (const StageCoef<R>*)fws;
   ra.ny = p.ny;
   ra.kf = (R)pl.kappa_f;
   ra.ks = (R)pl.kappa_sh;

@@ -109,7 +109,7 @@ struct RowAdjArgs {
   const cx<R>* ua;        // forward state: u_{s_second} if s_second >= 0, else y_{s_first}
   const cx<R>* ub;
   const Tw<R>* tw;
-  const cx<R>* phase;     // [nz][5] exp(-i phi)
+  const StageCoef<R>* phase;  // [nz][5] coupling factors at the stage points
   double* gp_first;       // [gridDim.x][2] {dL/dphi, dL/dphi * t} of the first half-step, or null
   double* gp_second;      // same for the second half-step, or null
   int ny;
@@ -324,7 +324,7 @@ struct RowAdjTArgs {
 template <typename R, bool TH>
 struct AdjPre {
   cx<R> ua, ub;
-  HalfStepPhase<R> e1, e2;   // table values; the coefficients are formed at use
+  HalfStep<R> c1, c2;        // coupling factors of both half-steps
   R psi, t2, t1;             // Psi and the raw samples T of both steps
   Carry<R> cr;
 };
@@ -334,8 +334,8 @@ struct AdjPre {
 // no wait on them stands before the loads that follow them.
 template <typename R, bool TH>
 __device__ __forceinline__ void adj_load_table(const RowAdjArgs<R>& p, AdjPre<R, TH>& a) {
-  a.e1 = half_step_phase<R>(gp(p.phase) + 5 * max(p.s_first, 0), p.full ? 2 : 1);
-  a.e2 = half_step_phase<R>(gp(p.phase) + 5 * max(p.s_second, 0) + 2);
+  a.c1 = half_step_coefs<R>(gp(p.phase) + 5 * max(p.s_first, 0), p.full ? 2 : 1);
+  a.c2 = half_step_coefs<R>(gp(p.phase) + 5 * max(p.s_second, 0) + 2);
 }
 template <typename R, bool TH>
 __device__ __forceinline__ void adj_load_cell(const RowAdjArgs<R>& p, const RowAdjTArgs<R>& q,
@@ -370,8 +370,8 @@ __device__ __forceinline__ void adj_cell(const RowAdjArgs<R>& p, const RowAdjTAr
   const cx<R> ub = pre.ub;
   cx<R> ya = ua, yb = ub;
   if constexpr (!TH) {
-    const HalfStep<R> c1 = coefs_of(pre.e1, p.kf, p.ks);
-    const HalfStep<R> c2 = coefs_of(pre.e2, p.kf, p.ks);
+    const HalfStep<R>& c1 = pre.c1;
+    const HalfStep<R>& c2 = pre.c2;
     if (p.s_second >= 0) rk4_cell(ya, yb, c2, p.tf, p.ts, h, und);
     R g = 0, gt = 0;
     if (p.s_first >= 0) {
@@ -395,7 +395,7 @@ __device__ __forceinline__ void adj_cell(const RowAdjArgs<R>& p, const RowAdjTAr
     if (p.s_second >= 0) {
       const R dT = pre.t2 - q.t_ref;
       const cx<R> step = expi_neg_small(thermal_dk(dT, q.dk) * qdz), st2 = step * step;
-      c2 = thermal_coefs(pre.e2, p.kf, p.ks, rho * st2, step, dT, q.lens_f, q.lens_sh);
+      c2 = thermal_coefs(pre.c2, rho * st2, step, dT, q.lens_f, q.lens_sh);
       rk4_cell_t(ya, yb, c2, p.tf, p.ts, h, und);
       rho = rho * (st2 * st2);
     }
@@ -403,7 +403,7 @@ __device__ __forceinline__ void adj_cell(const RowAdjArgs<R>& p, const RowAdjTAr
       const R dT = pre.t1 - q.t_ref;
       const int st = p.full ? 2 : 1;
       const HalfStepT<R> c1 =
-          thermal_coefs(pre.e1, p.kf, p.ks, rho, expi_neg_small(thermal_dk(dT, q.dk) * (qdz * st)),
+          thermal_coefs(pre.c1, rho, expi_neg_small(thermal_dk(dT, q.dk) * (qdz * st)),
                         dT, q.lens_f, q.lens_sh);
       R g = 0, gt = 0, gl = 0;
       rk4_vjp_t(ya, yb, la, lb, c1, p.tf, p.ts, q.lens_f, q.lens_sh, h * (R)st, und, (R)0, g, gt,

@@ -206,7 +206,7 @@ static int build_info(int n, shg_plan* const* plans, BatchPlanInfo& bi) {
   for (int i = 0; i < n; ++i) {
     const Plan& pl = *reinterpret_cast<const Plan*>(plans[i]);
     bi.phase_at[i] = off;
-    off += align256((size_t)pl.p.nz * 5 * csize);
+    off += align256((size_t)pl.p.nz * 5 * 2 * csize);   // [nz][5] StageCoef
     bi.part_at[i] = off;
     off += align256((size_t)pl.p.ny * 2 * sizeof(double));
   }
@@ -265,7 +265,7 @@ static int enqueue_batch(int n, shg_plan* const* plans, void* const* a_f, void* 
       r.ain = r.aout = (cx<R>*)a_f[i];
       r.bin = r.bout = (cx<R>*)a_sh[i];
       r.tw = (const Tw<R>*)pl.tw_x;
-      r.phase = (const cx<R>*)(ws + bi.phase_at[i]);
+      r.phase = (const StageCoef<R>*)(ws + bi.phase_at[i]);
       r.ny = pl.p.ny;
       r.kf = (R)pl.kappa_f;
       r.ks = (R)pl.kappa_sh;

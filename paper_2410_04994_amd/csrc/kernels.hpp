@@ -41,43 +41,24 @@ struct HalfStep {
   cx<R> cf[3], cs[3];
 };
 
-// e = exp(-i phi): cf = i kappa_F e, cs = i kappa_SH conj(e).  The stage
-// points are e[0], e[stride], e[2 stride] of the step's 5-point table: stride 1
-// for a half-step, 2 for a full step (L/2 - N - L/2 order).
-// The table values themselves: loaded early, turned into coefficients late.
+// Coupling factors at one stage point of the per-step table: with
+// e = exp(-i phi), cf = i kappa_F e and cs = i kappa_SH conj(e), formed in FP64
+// when the table is built and rounded once.  A step has 5 points (z_s + k dz/4,
+// k = 0..4); a half-step uses points 0, 1, 2 or 2, 3, 4 (stride 1), a full step
+// of the L/2 - N - L/2 order points 0, 2, 4 (stride 2).
 template <typename R>
-struct HalfStepPhase {
-  cx<R> e[3];
+struct StageCoef {
+  cx<R> cf, cs;
 };
 
 template <typename R, typename P>
-__device__ __forceinline__ HalfStepPhase<R> half_step_phase(P __restrict__ e, int stride = 1) {
-  HalfStepPhase<R> h;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) h.e[k] = gload(e + k * stride);
-  return h;
-}
-
-template <typename R>
-__device__ __forceinline__ HalfStep<R> coefs_of(const HalfStepPhase<R>& ph, R kf, R ks) {
+__device__ __forceinline__ HalfStep<R> half_step_coefs(P __restrict__ e, int stride = 1) {
   HalfStep<R> h;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    h.cf[k] = {-kf * ph.e[k].im, kf * ph.e[k].re};
-    h.cs[k] = {ks * ph.e[k].im, ks * ph.e[k].re};
-  }
-  return h;
-}
-
-template <typename R, typename P>
-__device__ __forceinline__ HalfStep<R> half_step_coefs(P __restrict__ e, R kf, R ks,
-                                                       int stride = 1) {
-  HalfStep<R> h;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const cx<R> ek = gload(e + k * stride);
-    h.cf[k] = {-kf * ek.im, kf * ek.re};
-    h.cs[k] = {ks * ek.im, ks * ek.re};
+    const StageCoef<R> c = gload(e + k * stride);
+    h.cf[k] = c.cf;
+    h.cs[k] = c.cs;
   }
   return h;
 }
@@ -218,24 +199,22 @@ __device__ __forceinline__ cx<R> expi_neg_small(R x) {
 }
 
 // Stage coefficients of one cell's half-step or full step with a temperature
-// field: ph the uniform table values at the three stage points, rho =
-// exp(-i phase) at the first stage,
-// step = exp(-i dkc qdz) the advance from stage to stage (qdz = dz/4 for a
-// half-step, dz/2 for a full step) and dT the lens sample.  The phase at the
-// start of a step is the carried Psi of the cell, exp(-i Psi) is formed once
-// per pass, and the later stages and the next step's start follow by products
-// of step: the second half of a step starts at step^2, the next step at
-// step^4 of the start of this one.
+// field: u the uniform coupling factors at the three stage points, rho =
+// exp(-i phase) of the cell's own phase at the first stage, step = exp(-i dkc
+// qdz) the advance from stage to stage (qdz = dz/4 for a half-step, dz/2 for a
+// full step) and dT the lens sample: cf = u.cf rho, cs = u.cs conj(rho).  The
+// phase at the start of a step is the carried Psi of the cell, exp(-i Psi) is
+// formed once per pass, and the later stages and the next step's start follow
+// by products of step: the second half of a step starts at step^2, the next
+// step at step^4 of the start of this one.
 template <typename R>
-__device__ __forceinline__ HalfStepT<R> thermal_coefs(const HalfStepPhase<R>& ph, R kf, R ks,
-                                                      cx<R> rho, cx<R> step, R dT, R lens_f,
-                                                      R lens_sh) {
+__device__ __forceinline__ HalfStepT<R> thermal_coefs(const HalfStep<R>& u, cx<R> rho, cx<R> step,
+                                                      R dT, R lens_f, R lens_sh) {
   HalfStepT<R> h;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const cx<R> ek = ph.e[k] * rho;
-    h.cf[k] = {-kf * ek.im, kf * ek.re};
-    h.cs[k] = {ks * ek.im, ks * ek.re};
+    h.cf[k] = u.cf[k] * rho;
+    h.cs[k] = u.cs[k] * conjg(rho);
     rho = rho * step;
   }
   h.gf = lens_f * dT;
@@ -285,7 +264,7 @@ struct RowArgs {
   cx<R>* tap_a;           // optional: real-space state before the second half-step
   cx<R>* tap_b;
   const Tw<R>* tw;        // W_nx^k, k = 0..nx-1
-  const cx<R>* phase;     // [nz][5] exp(-i phi) at z_s + {0, 1/4, 1/2, 3/4, 1} dz
+  const StageCoef<R>* phase;  // [nz][5] coupling factors at z_s + {0, 1/4, 1/2, 3/4, 1} dz
   double* partials;       // [gridDim.x][2] sums of |A|^2 (last pass), or null
   int ny;
   int s_second;           // step whose second half-step runs here, or -1
@@ -377,8 +356,8 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
   const int stf = p.full ? 2 : 1;
   HalfStep<R> c2{}, c1{};
   if constexpr (!TH) {
-    if (p.s_second >= 0) c2 = half_step_coefs(gp(p.phase) + 5 * p.s_second + 2, p.kf, p.ks);
-    if (p.s_first >= 0) c1 = half_step_coefs(gp(p.phase) + 5 * p.s_first, p.kf, p.ks, stf);
+    if (p.s_second >= 0) c2 = half_step_coefs<R>(gp(p.phase) + 5 * p.s_second + 2);
+    if (p.s_first >= 0) c1 = half_step_coefs<R>(gp(p.phase) + 5 * p.s_first, stf);
   }
   if (p.inv_in) {
     fft_pre<R, N, G, true, 1, (G <= 64)>(va, a0, a1, t, twr);
@@ -407,7 +386,7 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
         const R dkc = thermal_dk(dT, p.dk);
         const cx<R> step = expi_neg_small(dkc * qdz), st2 = step * step;
         const HalfStepT<R> c =
-            thermal_coefs(half_step_phase<R>(p.phase + 5 * p.s_second + 2), p.kf, p.ks, rho * st2,
+            thermal_coefs(half_step_coefs<R>(gp(p.phase) + 5 * p.s_second + 2), rho * st2,
                           step, dT, p.lens_f, p.lens_sh);
         rk4_cell_t(va[m], vb[m], c, p.tf, p.ts, p.h, und);
         psi += dkc * p.dz;
@@ -419,7 +398,7 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
         const R dkc = thermal_dk(dT, p.dk);
         const int st = p.full ? 2 : 1;
         const HalfStepT<R> c =
-            thermal_coefs(half_step_phase<R>(p.phase + 5 * p.s_first, st), p.kf, p.ks, rho,
+            thermal_coefs(half_step_coefs<R>(gp(p.phase) + 5 * p.s_first, st), rho,
                           expi_neg_small(dkc * (qdz * st)), dT, p.lens_f, p.lens_sh);
         rk4_cell_t(va[m], vb[m], c, p.tf, p.ts, p.h * st, und);
         if (p.full) psi += dkc * p.dz;
@@ -538,12 +517,12 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
   cx<R> a, b;
   TwRegs<R, N, G> twr;
   if (fth) tw_load(twr, t, p.tw);
-  // the table values of both half-steps are loaded here, unconditionally (a
-  // step index < 0 reads step 0, unused), and turned into coefficients after
-  // the transform, so that no wait on them stands before the field loads
+  // the coupling factors of both half-steps are loaded here, unconditionally
+  // (a step index < 0 reads step 0, unused), so that no wait on them stands
+  // before the field loads
   const int stf = p.full ? 2 : 1;
-  const HalfStepPhase<R> ph2 = half_step_phase<R>(gp(p.phase) + 5 * max(p.s_second, 0) + 2);
-  const HalfStepPhase<R> ph1 = half_step_phase<R>(gp(p.phase) + 5 * max(p.s_first, 0), stf);
+  const HalfStep<R> c2 = half_step_coefs<R>(gp(p.phase) + 5 * max(p.s_second, 0) + 2);
+  const HalfStep<R> c1 = half_step_coefs<R>(gp(p.phase) + 5 * max(p.s_first, 0), stf);
   // with a temperature field: the cell's Psi and its two samples, raw, loaded
   // after the field loads (unconditionally, like the table values), so that
   // the transform waits only for the fields
@@ -593,7 +572,7 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
       const R dkc = thermal_dk(dT, p.dk);
       const cx<R> step = expi_neg_small(dkc * qdz), st2 = step * step;
       const HalfStepT<R> c2t =
-          thermal_coefs(ph2, p.kf, p.ks, rho * st2, step, dT, p.lens_f, p.lens_sh);
+          thermal_coefs(c2, rho * st2, step, dT, p.lens_f, p.lens_sh);
       rk4_cell_t(a, b, c2t, p.tf, p.ts, p.h, und);
       psi += dkc * p.dz;
       rho = rho * (st2 * st2);
@@ -602,7 +581,7 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
     if (p.s_first >= 0) {
       const R dT = th_t1 - p.t_ref;
       const R dkc = thermal_dk(dT, p.dk);
-      const HalfStepT<R> c1t = thermal_coefs(ph1, p.kf, p.ks, rho,
+      const HalfStepT<R> c1t = thermal_coefs(c1, rho,
                                              expi_neg_small(dkc * (qdz * stf)), dT, p.lens_f,
                                              p.lens_sh);
       rk4_cell_t(a, b, c1t, p.tf, p.ts, p.h * stf, und);
@@ -611,8 +590,6 @@ __device__ __forceinline__ void row_wide_body(const RowArgs<R>& p, int blk) {
     // Psi at the start of the newest step touched
     if (p.s_second >= 0 || (p.full && p.s_first >= 0)) p.psi[idx] = psi;
   } else {
-    const HalfStep<R> c2 = coefs_of(ph2, p.kf, p.ks);
-    const HalfStep<R> c1 = coefs_of(ph1, p.kf, p.ks);
     if (p.s_second >= 0) rk4_cell(a, b, c2, p.tf, p.ts, p.h, und);
     if (p.heat) gp(p.heat)[idx] = heat_density(a, b, p);
     if (p.s_first >= 0) rk4_cell(a, b, c1, p.tf, p.ts, p.h * stf, und);
@@ -731,11 +708,13 @@ __global__ void __launch_bounds__(G * TC) col_pass(ColArgs<R> p) {
 
 // ---------------------------------------------------------------- phase table
 // Accumulated mismatch phase (Eq. 3) for a mismatch constant within each step:
-// Phi_s = sum_{s' < s} dk_s' dz (FP64 chunked scan in one block), and
-// out[5 s + k] = exp(-i (Phi_s + dk_s k dz / 4)), k = 0..4.
+// Phi_s = sum_{s' < s} dk_s' dz (FP64 chunked scan in one block), and the
+// coupling factors at phi = Phi_s + dk_s k dz / 4, k = 0..4: out[5 s + k] =
+// {i kf exp(-i phi), i ks exp(+i phi)}, formed in FP64 and rounded once.
 template <typename R>
 __device__ __forceinline__ void phase_table_body(const double* __restrict__ dk_z, double dk0,
-                                                 int nz, double dz, cx<R>* __restrict__ out) {
+                                                 int nz, double dz, double kf, double ks,
+                                                 StageCoef<R>* __restrict__ out) {
   __shared__ double part[256];
   const auto dkg = gp(dk_z);
   const auto og = gp(out);
@@ -762,7 +741,9 @@ __device__ __forceinline__ void phase_table_body(const double* __restrict__ dk_z
     for (int k = 0; k < 5; ++k) {
       double sn, cs;
       sincos(phi + dk * (0.25 * k * dz), &sn, &cs);
-      gstore(og + (5 * s + k), cx<R>{(R)cs, (R)(-sn)});
+      // e = cs - i sn: i kf e = kf (sn + i cs), i ks conj(e) = ks (-sn + i cs)
+      gstore(og + (5 * s + k),
+             StageCoef<R>{{(R)(kf * sn), (R)(kf * cs)}, {(R)(-ks * sn), (R)(ks * cs)}});
     }
     phi += dk * dz;
   }
@@ -770,8 +751,9 @@ __device__ __forceinline__ void phase_table_body(const double* __restrict__ dk_z
 
 template <typename R>
 __global__ void __launch_bounds__(256) phase_table(const double* __restrict__ dk_z, double dk0,
-                                                   int nz, double dz, cx<R>* __restrict__ out) {
-  phase_table_body<R>(dk_z, dk0, nz, dz, out);
+                                                   int nz, double dz, double kf, double ks,
+                                                   StageCoef<R>* __restrict__ out) {
+  phase_table_body<R>(dk_z, dk0, nz, dz, kf, ks, out);
 }
 
 // ---------------------------------------------------------------- powers
@@ -882,7 +864,8 @@ __global__ void __launch_bounds__(G * TC) col_pass_batch(const BatchInst<R>* __r
 template <typename R>
 __global__ void __launch_bounds__(256) phase_table_batch(const BatchInst<R>* __restrict__ inst) {
   const BatchInst<R>& I = inst[blockIdx.x];
-  phase_table_body<R>(I.dk_z, I.dk0, I.nz, I.dz, const_cast<cx<R>*>(I.row.phase));
+  phase_table_body<R>(I.dk_z, I.dk0, I.nz, I.dz, (double)I.row.kf, (double)I.row.ks,
+                      const_cast<StageCoef<R>*>(I.row.phase));
 }
 
 template <typename R>

@@ -500,7 +500,7 @@ void free_plan_tables(Plan& pl) {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 size_t forward_ws_bytes(const Plan& pl) {
-  const size_t phase = (size_t)pl.p.nz * 5 * 2 * pl.real_bytes;
+  const size_t phase = (size_t)pl.p.nz * 5 * 4 * pl.real_bytes;   // [nz][5] StageCoef
   const size_t parts = (size_t)pl.p.ny * 2 * sizeof(double);
   const size_t psi = (size_t)pl.p.nx * pl.p.ny * pl.real_bytes;
   return align256(phase) + align256(parts) + align256(psi);
@@ -511,13 +511,14 @@ static int enqueue_forward_t(Plan& pl, const FwdIO& io, const double* dk_z, int 
                              char* ws, double* powers, hipStream_t st, bool make_phase,
                              bool timed) {
   const shg_params& p = pl.p;
-  cx<R>* phase = (cx<R>*)ws;
-  double* partials = (double*)(ws + align256((size_t)p.nz * 5 * sizeof(cx<R>)));
-  R* psi = (R*)(ws + align256((size_t)p.nz * 5 * sizeof(cx<R>)) +
+  StageCoef<R>* phase = (StageCoef<R>*)ws;
+  double* partials = (double*)(ws + align256((size_t)p.nz * 5 * sizeof(StageCoef<R>)));
+  R* psi = (R*)(ws + align256((size_t)p.nz * 5 * sizeof(StageCoef<R>)) +
                 align256((size_t)p.ny * 2 * sizeof(double)));
   if (make_phase) {
+    // kappa as the kernels' real type, like the batch's table
     hipLaunchKernelGGL((phase_table<R>), dim3(1), dim3(256), 0, st, dk_z, p.dk0, p.nz, pl.dz,
-                       phase);
+                       (double)(R)pl.kappa_f, (double)(R)pl.kappa_sh, phase);
   }
   const size_t n2 = (size_t)p.nx * p.ny;
   cx<R>* wa = (cx<R>*)io.a_work;

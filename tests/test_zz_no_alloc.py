@@ -65,8 +65,8 @@ def test_noalloc_rejects_a_workspace_beyond_the_static_array():
     from paper_2410_04994_amd import Plan
     from paper_2410_04994_amd.binding import ShgError
 
-    # 512 x 512 complex128 needs 2 MiB for the thermal phase plus 80 B per
-    # step of phase table: above 4 MiB at nz = 30000 (rejected before launch)
+    # 512 x 512 complex128 needs 2 MiB for the thermal phase plus 160 B per
+    # step of stage coefficients: above 4 MiB at nz = 30000 (rejected before launch)
     wl = workloads.c2_plain_c64().with_(nx=512, ny=512, nz=30000)
     plan = Plan(wl.params(), "c128")
     assert plan.workspace_bytes() > 4 << 20
