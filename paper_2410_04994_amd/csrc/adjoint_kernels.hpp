@@ -58,7 +58,7 @@ __device__ __forceinline__ void rk4_vjp_u(cx<R> a, cx<R> b, cx<R>& la, cx<R>& lb
   const cx<R> u3a = a + scale(k2a, h2), u3b = b + scale(k2b, h2);
   nl_rhs(u3a, u3b, c.cf[1], c.cs[1], tf, ts, UND, k3a, k3b);
   const cx<R> u4a = a + scale(k3a, h), u4b = b + scale(k3b, h);
-  const R h6 = h / (R)6, h3 = h / (R)3;
+  const R h6 = h * (R)(1.0 / 6.0), h3 = h * (R)(1.0 / 3.0);
   cx<R> ga, gb;
   R dp;
   // stage 4
@@ -254,7 +254,7 @@ __device__ __forceinline__ void rk4_vjp_t_u(cx<R> a, cx<R> b, cx<R>& la, cx<R>& 
   const cx<R> u3a = a + scale(k2a, h2), u3b = b + scale(k2b, h2);
   nl_rhs_t(u3a, u3b, c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, UND, k3a, k3b);
   const cx<R> u4a = a + scale(k3a, h), u4b = b + scale(k3b, h);
-  const R h6 = h / (R)6, h3 = h / (R)3;
+  const R h6 = h * (R)(1.0 / 6.0), h3 = h * (R)(1.0 / 3.0);
   cx<R> ga, gb;
   R dp, dl;
   cx<R> kba = scale(la, h6), kbb = scale(lb, h6);

@@ -74,7 +74,7 @@ __device__ __forceinline__ void rk4_cell_u(cx<R>& a, cx<R>& b, const HalfStep<R>
   nl_rhs(a + scale(k1a, h2), b + scale(k1b, h2), c.cf[1], c.cs[1], tf, ts, UND, k2a, k2b);
   nl_rhs(a + scale(k2a, h2), b + scale(k2b, h2), c.cf[1], c.cs[1], tf, ts, UND, k3a, k3b);
   nl_rhs(a + scale(k3a, h), b + scale(k3b, h), c.cf[2], c.cs[2], tf, ts, UND, k4a, k4b);
-  const R h6 = h / (R)6;
+  const R h6 = h * (R)(1.0 / 6.0);   // a product: a division is ten instructions
   a = a + scale(k1a + scale(k2a + k3a, (R)2) + k4a, h6);
   b = b + scale(k1b + scale(k2b + k3b, (R)2) + k4b, h6);
 }
@@ -243,7 +243,7 @@ __device__ __forceinline__ void rk4_cell_t_u(cx<R>& a, cx<R>& b, const HalfStepT
            k3b);
   nl_rhs_t(a + scale(k3a, h), b + scale(k3b, h), c.cf[2], c.cs[2], tf, ts, c.gf, c.gs, UND, k4a,
            k4b);
-  const R h6 = h / (R)6;
+  const R h6 = h * (R)(1.0 / 6.0);   // a product: a division is ten instructions
   a = a + scale(k1a + scale(k2a + k3a, (R)2) + k4a, h6);
   b = b + scale(k1b + scale(k2b + k3b, (R)2) + k4b, h6);
 }
