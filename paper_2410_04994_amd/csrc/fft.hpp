@@ -360,6 +360,18 @@ __device__ __forceinline__ T* pick_ptr(int f, T* p0, T* p1) {
   return (T*)(a + (uintptr_t)(unsigned)f * (b - a));
 }
 
+// The same choice for a flag that is uniform over the wavefront (held in a
+// scalar register): a select of two indexed kernel arguments would become a
+// scalar load from the argument segment at a computed offset, a dependent
+// memory round trip ahead of every load that uses the pointer.
+template <typename T>
+__device__ __forceinline__ T* pick_ptr_uniform(int f, T* p0, T* p1) {
+  f = __builtin_amdgcn_readfirstlane(f);
+  asm volatile("" : "+s"(f));
+  const uintptr_t a = (uintptr_t)p0, b = (uintptr_t)p1;
+  return (T*)(a + (uintptr_t)(unsigned)f * (b - a));
+}
+
 // Index of the transform a thread works on: G threads per transform, so with
 // G >= 64 the index is uniform over each wavefront and is read as a scalar.
 template <int G>

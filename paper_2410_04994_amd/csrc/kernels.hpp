@@ -662,12 +662,14 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& p) {
   const int c = threadIdx.x % TC;
   const int t = threadIdx.x / TC;
   const int lin = xcd_linear_block(blockIdx.x, gridDim.x);
-  const int field = lin / p.tiles;
+  // two fields: the block's field by a comparison (no integer division) and
+  // its pointers chosen arithmetically among the kernel arguments (no
+  // dependent load ahead of the field loads); element offsets fit in 32 bits
+  // (a field holds at most 512 x 512 elements)
+  const int field = lin >= p.tiles ? 1 : 0;
   const int tile = lin - field * p.tiles;
   const int x = tile * TC + c;
-  // the field pointer is uniform per block; element offsets fit in 32 bits
-  // (a field holds at most 512 x 512 elements)
-  const auto fld = gp(p.f[field]);
+  const auto fld = gp(pick_ptr_uniform(field, p.f[0], p.f[1]));
   const unsigned o0 = (unsigned)x + (unsigned)t * (unsigned)p.nx;
   const unsigned og = (unsigned)(G * p.nx);
   cx<R> v[E];
@@ -675,8 +677,8 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& p) {
   for (int m = 0; m < E; ++m) v[m] = gload(fld + (o0 + (unsigned)m * og));
   // diffraction + linear loss (Eq. A.4): the FP64 product m_x m_y of this
   // thread's bins, formed before the transforms so that its loads overlap FFT_y
-  const auto mxp = gp(p.mx[field]);
-  const auto myp = gp(p.my[field]);
+  const auto mxp = gp(pick_ptr_uniform(field, p.mx[0], p.mx[1]));
+  const auto myp = gp(pick_ptr_uniform(field, p.my[0], p.my[1]));
   const double sgn = p.conj_prop ? -1.0 : 1.0;
   const double mxr = mxp[2 * x], mxi = sgn * mxp[2 * x + 1];
   double mr[E], mi[E];
