@@ -223,8 +223,8 @@ int shg_propagate_adjoint(shg_plan *plan, const void *a_f_in, const void *a_sh_i
  *   plans[i], a_f[i], a_sh[i]  as for shg_propagate (fields updated in place)
  *   dk_z[i]                    per-instance [nz_i] profile, or NULL entries /
  *                              NULL array for the plans' dk0
- *   workspace                  shg_batch_workspace_bytes(...) bytes (phase
- *                              tables and power partials, rewritten by every
+ *   workspace                  shg_batch_workspace_bytes(...) bytes (stage-
+ *                              coefficient tables and power partials, rewritten by every
  *                              call), or NULL for a buffer kept by plans[0]
  *   powers                     [n][2] double exit powers, or NULL
  * The first call with a set of arguments (plans, fields, profiles, workspace,
