@@ -41,23 +41,46 @@ __device__ __forceinline__ void nl_vjp(cx<R> a, cx<R> b, cx<R> cf, cx<R> cs, R t
   }
 }
 
-// Reverse of one RK4 half-step (forward stages recomputed from the input y).
-// (a, b)    in: input state y of the half-step
+// Stage inputs u2, u3, u4 of one RK4 half-step (u1 is its input).
+template <typename R>
+struct Rk4Stages {
+  cx<R> u2a, u2b, u3a, u3b, u4a, u4b;
+};
+
+// The forward half-step of rk4_cell that also keeps its stage inputs, for a
+// later pull-back through the same half-step.
+template <bool UND, typename R>
+__device__ __forceinline__ void rk4_cell_keep_u(cx<R>& a, cx<R>& b, const HalfStep<R>& c, R tf,
+                                                R ts, R h, Rk4Stages<R>& st) {
+  const R h2 = h * (R)0.5;
+  cx<R> k1a, k1b, k2a, k2b, k3a, k3b, k4a, k4b;
+  nl_rhs(a, b, c.cf[0], c.cs[0], tf, ts, UND, k1a, k1b);
+  st.u2a = a + scale(k1a, h2);
+  st.u2b = b + scale(k1b, h2);
+  nl_rhs(st.u2a, st.u2b, c.cf[1], c.cs[1], tf, ts, UND, k2a, k2b);
+  st.u3a = a + scale(k2a, h2);
+  st.u3b = b + scale(k2b, h2);
+  nl_rhs(st.u3a, st.u3b, c.cf[1], c.cs[1], tf, ts, UND, k3a, k3b);
+  st.u4a = a + scale(k3a, h);
+  st.u4b = b + scale(k3b, h);
+  nl_rhs(st.u4a, st.u4b, c.cf[2], c.cs[2], tf, ts, UND, k4a, k4b);
+  const R h6 = h * (R)(1.0 / 6.0);
+  a = a + scale(k1a + scale(k2a + k3a, (R)2) + k4a, h6);
+  b = b + scale(k1b + scale(k2b + k3b, (R)2) + k4b, h6);
+}
+
+// Reverse of one RK4 half-step whose stage inputs are known.
+// (a, b)    in: input state y of the half-step; st its stage inputs
 // (la, lb)  in: cotangent of the output; out: cotangent of the input
 // gphi, gphit accumulate dL/dphi and dL/dphi * t over the four stages, where
 // the stage points are t0, t0 + h/2, t0 + h/2, t0 + h.
 template <bool UND, typename R>
-__device__ __forceinline__ void rk4_vjp_u(cx<R> a, cx<R> b, cx<R>& la, cx<R>& lb,
-                                        const HalfStep<R>& c, R tf, R ts, R h, R t0,
-                                        R& gphi, R& gphit) {
+__device__ __forceinline__ void rk4_vjp_from_u(cx<R> a, cx<R> b, const Rk4Stages<R>& st,
+                                               cx<R>& la, cx<R>& lb, const HalfStep<R>& c, R tf,
+                                               R ts, R h, R t0, R& gphi, R& gphit) {
   const R h2 = h * (R)0.5;
-  cx<R> k1a, k1b, k2a, k2b, k3a, k3b;
-  nl_rhs(a, b, c.cf[0], c.cs[0], tf, ts, UND, k1a, k1b);
-  const cx<R> u2a = a + scale(k1a, h2), u2b = b + scale(k1b, h2);
-  nl_rhs(u2a, u2b, c.cf[1], c.cs[1], tf, ts, UND, k2a, k2b);
-  const cx<R> u3a = a + scale(k2a, h2), u3b = b + scale(k2b, h2);
-  nl_rhs(u3a, u3b, c.cf[1], c.cs[1], tf, ts, UND, k3a, k3b);
-  const cx<R> u4a = a + scale(k3a, h), u4b = b + scale(k3b, h);
+  const cx<R> u2a = st.u2a, u2b = st.u2b, u3a = st.u3a, u3b = st.u3b, u4a = st.u4a,
+              u4b = st.u4b;
   const R h6 = h * (R)(1.0 / 6.0), h3 = h * (R)(1.0 / 3.0);
   cx<R> ga, gb;
   R dp;
@@ -94,12 +117,44 @@ __device__ __forceinline__ void rk4_vjp_u(cx<R> a, cx<R> b, cx<R>& la, cx<R>& lb
   la = la + sa;
   lb = lb + sb;
 }
+// Reverse of one RK4 half-step with its stage inputs recomputed from y.
+template <bool UND, typename R>
+__device__ __forceinline__ void rk4_vjp_u(cx<R> a, cx<R> b, cx<R>& la, cx<R>& lb,
+                                        const HalfStep<R>& c, R tf, R ts, R h, R t0,
+                                        R& gphi, R& gphit) {
+  const R h2 = h * (R)0.5;
+  cx<R> k1a, k1b, k2a, k2b, k3a, k3b;
+  Rk4Stages<R> st;
+  nl_rhs(a, b, c.cf[0], c.cs[0], tf, ts, UND, k1a, k1b);
+  st.u2a = a + scale(k1a, h2);
+  st.u2b = b + scale(k1b, h2);
+  nl_rhs(st.u2a, st.u2b, c.cf[1], c.cs[1], tf, ts, UND, k2a, k2b);
+  st.u3a = a + scale(k2a, h2);
+  st.u3b = b + scale(k2b, h2);
+  nl_rhs(st.u3a, st.u3b, c.cf[1], c.cs[1], tf, ts, UND, k3a, k3b);
+  st.u4a = a + scale(k3a, h);
+  st.u4b = b + scale(k3b, h);
+  rk4_vjp_from_u<UND>(a, b, st, la, lb, c, tf, ts, h, t0, gphi, gphit);
+}
 template <typename R>
 __device__ __forceinline__ void rk4_vjp(cx<R> a, cx<R> b, cx<R>& la, cx<R>& lb,
                                         const HalfStep<R>& c, R tf, R ts, R h, bool und, R t0,
                                         R& gphi, R& gphit) {
   if (und) rk4_vjp_u<true>(a, b, la, lb, c, tf, ts, h, t0, gphi, gphit);
   else rk4_vjp_u<false>(a, b, la, lb, c, tf, ts, h, t0, gphi, gphit);
+}
+template <typename R>
+__device__ __forceinline__ void rk4_cell_keep(cx<R>& a, cx<R>& b, const HalfStep<R>& c, R tf,
+                                              R ts, R h, bool und, Rk4Stages<R>& st) {
+  if (und) rk4_cell_keep_u<true>(a, b, c, tf, ts, h, st);
+  else rk4_cell_keep_u<false>(a, b, c, tf, ts, h, st);
+}
+template <typename R>
+__device__ __forceinline__ void rk4_vjp_from(cx<R> a, cx<R> b, const Rk4Stages<R>& st, cx<R>& la,
+                                             cx<R>& lb, const HalfStep<R>& c, R tf, R ts, R h,
+                                             bool und, R t0, R& gphi, R& gphit) {
+  if (und) rk4_vjp_from_u<true>(a, b, st, la, lb, c, tf, ts, h, t0, gphi, gphit);
+  else rk4_vjp_from_u<false>(a, b, st, la, lb, c, tf, ts, h, t0, gphi, gphit);
 }
 
 template <typename R>
@@ -242,18 +297,37 @@ __device__ __forceinline__ void nl_vjp_t(cx<R> a, cx<R> b, cx<R> cf, cx<R> cs, R
   }
 }
 
+// rk4_cell_t keeping its stage inputs (see rk4_cell_keep_u).
 template <bool UND, typename R>
-__device__ __forceinline__ void rk4_vjp_t_u(cx<R> a, cx<R> b, cx<R>& la, cx<R>& lb,
-                                          const HalfStepT<R>& c, R tf, R ts, R lf, R ls, R h,
-                                            R t0, R& gphi, R& gphit, R& glens) {
+__device__ __forceinline__ void rk4_cell_t_keep_u(cx<R>& a, cx<R>& b, const HalfStepT<R>& c, R tf,
+                                                  R ts, R h, Rk4Stages<R>& st) {
   const R h2 = h * (R)0.5;
-  cx<R> k1a, k1b, k2a, k2b, k3a, k3b;
+  cx<R> k1a, k1b, k2a, k2b, k3a, k3b, k4a, k4b;
   nl_rhs_t(a, b, c.cf[0], c.cs[0], tf, ts, c.gf, c.gs, UND, k1a, k1b);
-  const cx<R> u2a = a + scale(k1a, h2), u2b = b + scale(k1b, h2);
-  nl_rhs_t(u2a, u2b, c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, UND, k2a, k2b);
-  const cx<R> u3a = a + scale(k2a, h2), u3b = b + scale(k2b, h2);
-  nl_rhs_t(u3a, u3b, c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, UND, k3a, k3b);
-  const cx<R> u4a = a + scale(k3a, h), u4b = b + scale(k3b, h);
+  st.u2a = a + scale(k1a, h2);
+  st.u2b = b + scale(k1b, h2);
+  nl_rhs_t(st.u2a, st.u2b, c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, UND, k2a, k2b);
+  st.u3a = a + scale(k2a, h2);
+  st.u3b = b + scale(k2b, h2);
+  nl_rhs_t(st.u3a, st.u3b, c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, UND, k3a, k3b);
+  st.u4a = a + scale(k3a, h);
+  st.u4b = b + scale(k3b, h);
+  nl_rhs_t(st.u4a, st.u4b, c.cf[2], c.cs[2], tf, ts, c.gf, c.gs, UND, k4a, k4b);
+  const R h6 = h * (R)(1.0 / 6.0);
+  a = a + scale(k1a + scale(k2a + k3a, (R)2) + k4a, h6);
+  b = b + scale(k1b + scale(k2b + k3b, (R)2) + k4b, h6);
+}
+
+// rk4_vjp_from_u with the temperature-field terms (lens rates and their
+// derivative glens).
+template <bool UND, typename R>
+__device__ __forceinline__ void rk4_vjp_t_from_u(cx<R> a, cx<R> b, const Rk4Stages<R>& st,
+                                                 cx<R>& la, cx<R>& lb, const HalfStepT<R>& c,
+                                                 R tf, R ts, R lf, R ls, R h, R t0, R& gphi,
+                                                 R& gphit, R& glens) {
+  const R h2 = h * (R)0.5;
+  const cx<R> u2a = st.u2a, u2b = st.u2b, u3a = st.u3a, u3b = st.u3b, u4a = st.u4a,
+              u4b = st.u4b;
   const R h6 = h * (R)(1.0 / 6.0), h3 = h * (R)(1.0 / 3.0);
   cx<R> ga, gb;
   R dp, dl;
@@ -290,12 +364,45 @@ __device__ __forceinline__ void rk4_vjp_t_u(cx<R> a, cx<R> b, cx<R>& la, cx<R>& 
   la = la + sa;
   lb = lb + sb;
 }
+// Reverse of one temperature-field RK4 half-step, stage inputs recomputed.
+template <bool UND, typename R>
+__device__ __forceinline__ void rk4_vjp_t_u(cx<R> a, cx<R> b, cx<R>& la, cx<R>& lb,
+                                            const HalfStepT<R>& c, R tf, R ts, R lf, R ls, R h,
+                                            R t0, R& gphi, R& gphit, R& glens) {
+  const R h2 = h * (R)0.5;
+  cx<R> k1a, k1b, k2a, k2b, k3a, k3b;
+  Rk4Stages<R> st;
+  nl_rhs_t(a, b, c.cf[0], c.cs[0], tf, ts, c.gf, c.gs, UND, k1a, k1b);
+  st.u2a = a + scale(k1a, h2);
+  st.u2b = b + scale(k1b, h2);
+  nl_rhs_t(st.u2a, st.u2b, c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, UND, k2a, k2b);
+  st.u3a = a + scale(k2a, h2);
+  st.u3b = b + scale(k2b, h2);
+  nl_rhs_t(st.u3a, st.u3b, c.cf[1], c.cs[1], tf, ts, c.gf, c.gs, UND, k3a, k3b);
+  st.u4a = a + scale(k3a, h);
+  st.u4b = b + scale(k3b, h);
+  rk4_vjp_t_from_u<UND>(a, b, st, la, lb, c, tf, ts, lf, ls, h, t0, gphi, gphit, glens);
+}
 template <typename R>
 __device__ __forceinline__ void rk4_vjp_t(cx<R> a, cx<R> b, cx<R>& la, cx<R>& lb,
                                           const HalfStepT<R>& c, R tf, R ts, R lf, R ls, R h,
                                           bool und, R t0, R& gphi, R& gphit, R& glens) {
   if (und) rk4_vjp_t_u<true>(a, b, la, lb, c, tf, ts, lf, ls, h, t0, gphi, gphit, glens);
   else rk4_vjp_t_u<false>(a, b, la, lb, c, tf, ts, lf, ls, h, t0, gphi, gphit, glens);
+}
+template <typename R>
+__device__ __forceinline__ void rk4_cell_t_keep(cx<R>& a, cx<R>& b, const HalfStepT<R>& c, R tf,
+                                                R ts, R h, bool und, Rk4Stages<R>& st) {
+  if (und) rk4_cell_t_keep_u<true>(a, b, c, tf, ts, h, st);
+  else rk4_cell_t_keep_u<false>(a, b, c, tf, ts, h, st);
+}
+template <typename R>
+__device__ __forceinline__ void rk4_vjp_t_from(cx<R> a, cx<R> b, const Rk4Stages<R>& st,
+                                               cx<R>& la, cx<R>& lb, const HalfStepT<R>& c, R tf,
+                                               R ts, R lf, R ls, R h, bool und, R t0, R& gphi,
+                                               R& gphit, R& glens) {
+  if (und) rk4_vjp_t_from_u<true>(a, b, st, la, lb, c, tf, ts, lf, ls, h, t0, gphi, gphit, glens);
+  else rk4_vjp_t_from_u<false>(a, b, st, la, lb, c, tf, ts, lf, ls, h, t0, gphi, gphit, glens);
 }
 
 // Per-cell carry of the thermal reverse sweep:
@@ -372,7 +479,10 @@ __device__ __forceinline__ void adj_cell(const RowAdjArgs<R>& p, const RowAdjTAr
   if constexpr (!TH) {
     const HalfStep<R>& c1 = pre.c1;
     const HalfStep<R>& c2 = pre.c2;
-    if (p.s_second >= 0) rk4_cell(ya, yb, c2, p.tf, p.ts, h, und);
+    // the forward second half-step from u, keeping its stage inputs for its
+    // own pull-back below
+    Rk4Stages<R> stg2{};
+    if (p.s_second >= 0) rk4_cell_keep(ya, yb, c2, p.tf, p.ts, h, und, stg2);
     R g = 0, gt = 0;
     if (p.s_first >= 0) {
       rk4_vjp(ya, yb, la, lb, c1, p.tf, p.ts, p.full ? h + h : h, und, (R)0, g, gt);
@@ -382,7 +492,7 @@ __device__ __forceinline__ void adj_cell(const RowAdjArgs<R>& p, const RowAdjTAr
     if (p.s_second >= 0) {
       g = 0;
       gt = 0;
-      rk4_vjp(ua, ub, la, lb, c2, p.tf, p.ts, h, und, h, g, gt);
+      rk4_vjp_from(ua, ub, stg2, la, lb, c2, p.tf, p.ts, h, und, h, g, gt);
       acc[2] += (double)g;
       acc[3] += (double)gt;
     }
@@ -392,11 +502,12 @@ __device__ __forceinline__ void adj_cell(const RowAdjArgs<R>& p, const RowAdjTAr
     cx<R> rho = expi_neg(pre.psi);
     Carry<R> cr = pre.cr;
     HalfStepT<R> c2{};
+    Rk4Stages<R> stg2{};
     if (p.s_second >= 0) {
       const R dT = pre.t2 - q.t_ref;
       const cx<R> step = expi_neg_small(thermal_dk(dT, q.dk) * qdz), st2 = step * step;
       c2 = thermal_coefs(pre.c2, rho * st2, step, dT, q.lens_f, q.lens_sh);
-      rk4_cell_t(ya, yb, c2, p.tf, p.ts, h, und);
+      rk4_cell_t_keep(ya, yb, c2, p.tf, p.ts, h, und, stg2);
       rho = rho * (st2 * st2);
     }
     if (p.s_first >= 0) {
@@ -420,7 +531,8 @@ __device__ __forceinline__ void adj_cell(const RowAdjArgs<R>& p, const RowAdjTAr
     }
     if (p.s_second >= 0) {
       R g = 0, gt = 0, gl = 0;
-      rk4_vjp_t(ua, ub, la, lb, c2, p.tf, p.ts, q.lens_f, q.lens_sh, h, und, h, g, gt, gl);
+      rk4_vjp_t_from(ua, ub, stg2, la, lb, c2, p.tf, p.ts, q.lens_f, q.lens_sh, h, und, h, g, gt,
+                     gl);
       acc[2] += (double)g;
       acc[3] += (double)gt;
       cr.y = g;
