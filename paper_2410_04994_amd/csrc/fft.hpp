@@ -232,6 +232,13 @@ struct pick_radix {
                                                                : 2;
 };
 
+// Number of Stockham passes of an N-point transform at E elements per thread.
+template <int E, int REM>
+constexpr int stockham_passes() {
+  if constexpr (REM == 1) return 0;
+  else return 1 + stockham_passes<E, REM / pick_radix<E, REM>::value>();
+}
+
 // LDS index with one complex of padding per 16 (breaks power-of-two strides).
 __device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
 template <int N>

@@ -653,12 +653,15 @@ __device__ __forceinline__ int xcd_linear_block(int b, int nblk) {
 // Thread t * TC + c works on element rows t + G m of column c, so that the TC
 // columns of a row are read by adjacent lanes.  A block of at most 64 threads
 // is one wavefront, and its transforms then synchronise at wavefront level.
-template <typename R, int N, int G, int TC>
+template <typename R, int N, int G, int TC, bool LATE_MY = false>
 __device__ __forceinline__ void col_body(const ColArgs<R>& p) {
   constexpr bool WAVE = G * TC <= 64;
   constexpr int E = N / G;
   constexpr int P = padded_len<N>();
-  __shared__ cx<R> lds[2][P * TC];
+  // a transform of at most two Stockham passes writes and reads only b1, so
+  // b0 can share its buffer
+  constexpr int LB = stockham_passes<N / G, N>() > 2 ? 2 : 1;
+  __shared__ cx<R> lds[LB][P * TC];
   const int c = threadIdx.x % TC;
   const int t = threadIdx.x / TC;
   const int lin = xcd_linear_block(blockIdx.x, gridDim.x);
@@ -681,22 +684,37 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& p) {
   const auto myp = gp(pick_ptr_uniform(field, p.my[0], p.my[1]));
   const double sgn = p.conj_prop ? -1.0 : 1.0;
   const double mxr = mxp[2 * x], mxi = sgn * mxp[2 * x + 1];
-  double mr[E], mi[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int qy = t + G * m;
-    const double myr = myp[2 * qy], myi = sgn * myp[2 * qy + 1];
-    mr[m] = mxr * myr - mxi * myi;
-    mi[m] = mxr * myi + mxi * myr;
-  }
-  const LdsView<R, TC> b0{&lds[0][c]}, b1{&lds[1][c]};
+  const LdsView<R, TC> b0{&lds[0][c]}, b1{&lds[LB - 1][c]};
   TwRegs<R, N, G> twr;
   tw_load(twr, t, p.tw);
-  fft_pre<R, N, G, false, TC, WAVE>(v, b0, b1, t, twr);
+  // LATE_MY (the batch passes, bound by throughput): m_y is read after FFT_y,
+  // which keeps the 4 E registers of the product free for more resident
+  // wavefronts; the arithmetic is the same
+  if constexpr (!LATE_MY) {
+    double mr[E], mi[E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const double vr = (double)v[m].re, vi = (double)v[m].im;
-    v[m] = {(R)(vr * mr[m] - vi * mi[m]), (R)(vr * mi[m] + vi * mr[m])};
+    for (int m = 0; m < E; ++m) {
+      const int qy = t + G * m;
+      const double myr = myp[2 * qy], myi = sgn * myp[2 * qy + 1];
+      mr[m] = mxr * myr - mxi * myi;
+      mi[m] = mxr * myi + mxi * myr;
+    }
+    fft_pre<R, N, G, false, TC, WAVE>(v, b0, b1, t, twr);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const double vr = (double)v[m].re, vi = (double)v[m].im;
+      v[m] = {(R)(vr * mr[m] - vi * mi[m]), (R)(vr * mi[m] + vi * mr[m])};
+    }
+  } else {
+    fft_pre<R, N, G, false, TC, WAVE>(v, b0, b1, t, twr);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int qy = t + G * m;
+      const double myr = myp[2 * qy], myi = sgn * myp[2 * qy + 1];
+      const double mr = mxr * myr - mxi * myi, mi = mxr * myi + mxi * myr;
+      const double vr = (double)v[m].re, vi = (double)v[m].im;
+      v[m] = {(R)(vr * mr - vi * mi), (R)(vr * mi + vi * mr)};
+    }
   }
   fft_pre<R, N, G, true, TC, WAVE>(v, b0, b1, t, twr);
 #pragma unroll
@@ -844,12 +862,20 @@ __global__ void __launch_bounds__(WideShape<N>::threads) row_pass_batch_wide(
   row_wide_body<R, N, false>(p, blockIdx.x);
 }
 
+// Batch column passes of 16 elements per thread on 256-point columns need
+// about 170 VGPRs; a bound of three wavefronts per SIMD keeps them at 168
+// (three resident wavefronts instead of two).
+template <int N, int G>
+struct ColBatchWaves {
+  static constexpr int value = (N == 256 && N / G == 16) ? 3 : 1;
+};
+
 // Column pass after row boundary s: the full-step propagator, or in the
 // L/2 - N - L/2 order the half-step one for the opening (s = -1) and the
 // instance's last step (s = nz - 1).
 template <typename R, int N, int G, int TC>
-__global__ void __launch_bounds__(G * TC) col_pass_batch(const BatchInst<R>* __restrict__ inst,
-                                                         int s) {
+__global__ void __launch_bounds__(G * TC, (ColBatchWaves<N, G>::value))
+    col_pass_batch(const BatchInst<R>* __restrict__ inst, int s) {
   const BatchInst<R>& I = inst[blockIdx.y];
   if (I.lnl && (s < 0 || s == I.nz - 1)) {
     ColArgs<R> c = I.col;
@@ -857,9 +883,9 @@ __global__ void __launch_bounds__(G * TC) col_pass_batch(const BatchInst<R>* __r
       c.mx[w] = I.mxh[w];
       c.my[w] = I.myh[w];
     }
-    col_body<R, N, G, TC>(c);
+    col_body<R, N, G, TC, true>(c);
   } else {
-    col_body<R, N, G, TC>(I.col);
+    col_body<R, N, G, TC, true>(I.col);
   }
 }
 
