@@ -239,6 +239,18 @@ constexpr int stockham_passes() {
   else return 1 + stockham_passes<E, REM / pick_radix<E, REM>::value>();
 }
 
+// True when every Stockham pass but the last has one butterfly per thread
+// (radix = elements per thread; the last pass only reads into registers).  A
+// wavefront issues all LDS reads of such a pass before its writes and its LDS
+// operations complete in order, so a transform held by one wavefront can then
+// run its passes in place in a single buffer.
+template <int E, int REM>
+constexpr bool stockham_one_butterfly() {
+  constexpr int RP = pick_radix<E, REM>::value;
+  if constexpr (REM == RP) return true;
+  else return RP == E && stockham_one_butterfly<E, REM / RP>();
+}
+
 // LDS index with one complex of padding per 16 (breaks power-of-two strides).
 __device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
 template <int N>

@@ -333,7 +333,10 @@ template <typename R, int N, int G, int ROWS, bool TH = false>
 __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
   constexpr int E = N / G;
   constexpr int P = padded_len<N>();
-  __shared__ cx<R> lds[ROWS][2][2][P];
+  // transforms within one wavefront with one butterfly per thread and pass
+  // work in place: one LDS buffer per field instead of two
+  constexpr int LB = (G <= 64 && stockham_one_butterfly<E, N>()) ? 1 : 2;
+  __shared__ cx<R> lds[ROWS][2][LB][P];
   __shared__ double red[2 * ((G * ROWS + 63) / 64)];
   const int t = threadIdx.x % G;
   const int rr = threadIdx.x / G;
@@ -347,8 +350,8 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& p, int blk) {
     va[m] = gload(ain + (row + t + G * m));
     vb[m] = gload(bin + (row + t + G * m));
   }
-  const LdsView<R, 1> a0{&lds[rr][0][0][0]}, a1{&lds[rr][0][1][0]};
-  const LdsView<R, 1> b0{&lds[rr][1][0][0]}, b1{&lds[rr][1][1][0]};
+  const LdsView<R, 1> a0{&lds[rr][0][0][0]}, a1{&lds[rr][0][LB - 1][0]};
+  const LdsView<R, 1> b0{&lds[rr][1][0][0]}, b1{&lds[rr][1][LB - 1][0]};
   TwRegs<R, N, G> twr;
   tw_load(twr, t, p.tw);
   // stage coefficients of the uniform-mismatch half-steps, loaded before the
