@@ -161,6 +161,28 @@ def test_every_built_schedule_matches_the_oracle():
     assert tried >= 10
 
 
+@pytest.mark.parametrize("n", [32, 128, 512])
+def test_narrow_row_schedules_on_other_row_lengths(n):
+    """The narrow row passes run their Stockham passes in place in one LDS
+    buffer when a transform has one butterfly per thread in every pass but the
+    last: every built narrow row schedule on 32-, 128- and 512-point rows."""
+    base = workloads.c2_plain_c64()
+    wl = base.with_(nx=n, ny=64, nz=5, lx=base.lx * n / 256, ly=base.ly * 64 / 256)
+    plan = make_plan(wl)
+    a0, b0 = inputs(wl)
+    ref = run_oracle(wl, a0, b0)
+    tried = 0
+    for re_ in (4, 8, 16):
+        for rw in (64, 256):
+            try:
+                plan.set_schedule(re_, rw, 0, 0)
+            except Exception:
+                continue
+            compare(wl, run_gpu(plan, a0, b0), ref, "c64", plan.describe())
+            tried += 1
+    assert tried >= 3
+
+
 def test_invalid_step_range_and_fields():
     from paper_2410_04994_amd import ShgError
     wl = workloads.c2_plain_c64().with_(nx=64, ny=64, nz=10)
